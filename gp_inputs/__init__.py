@@ -1,0 +1,213 @@
+"""Seeded synthetic inputs for the Gross-Pitaevskii split step.
+
+This module holds only input construction (initial fields, random directions,
+workload descriptions).  It contains none of the method's arithmetic (no split
+step, no diagnostics) and imports neither the oracle nor the HIP library, so
+both sides can take their inputs from it.
+
+Initial conditions follow the paper's "Initial data preparation" section:
+
+* ``srp_fourier_theta`` -- smoothed random phase.  The paper interpolates random
+  control values with periodic cubic splines; the workloads here ask instead
+  for Gaussian random Fourier modes with |k| <= K, so theta is band-limited.
+  Recipe: numpy PCG64(seed); for every integer k with 0 < |k|^2 <= K^2 in
+  lexicographic (kz, ky, kx) order draw a, b ~ N(0, 1) and set
+  theta_hat_k = a + i b (folded mod N); Hermitian-symmetrise, zero the mean
+  mode, transform to real space and scale to rms(theta) = 1.  psi = exp(i theta).
+* ``tg_psi`` -- Taylor-Green ansatz: Clebsch potentials (eq. clebsch3d),
+  psi_e (eq. psie, tanh argument read as r / (sqrt(2) xi)), the product of
+  four shifted copies (eq. psi4) raised to [1/(2 pi alpha)] (eq. psitot3d),
+  evaluated directly on [0, 2 pi)^3; no imaginary-time relaxation.
+* ``rvr_psi`` -- random vortex-ring pairs: Pade profile (eq. Pade and its
+  coefficients), ring phase atan2(z~, r - R), pair psi_VR(z - d/2) conj
+  psi_VR(z + d/2), six mirror-conjugate images (eq. psiRP), random translation
+  by direct evaluation at (x - X) mod 2 pi, random axis permutation
+  (eq. psiRVR), product over pairs.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+__all__ = [
+    "grid", "srp_fourier_theta", "srp_mode_count", "tg_psi", "pade_f",
+    "PADE_A1", "PADE_A2", "PADE_B1", "rvr_psi", "rvr_draws", "random_field",
+    "random_real", "alpha_beta_from_xi", "alpha_beta_table1", "WORKLOADS",
+]
+
+TWO_PI = 2.0 * math.pi
+
+
+def grid(n: int) -> np.ndarray:
+    """Grid coordinates x_j = 2 pi j / n."""
+    return TWO_PI * np.arange(n, dtype=np.float64) / n
+
+
+# ------------------------------------------------------------------ SRP
+def _modes(K: int):
+    r = range(-K, K + 1)
+    return [(kz, ky, kx) for kz in r for ky in r for kx in r
+            if 0 < kz * kz + ky * ky + kx * kx <= K * K]
+
+
+def srp_mode_count(K: int) -> int:
+    return len(_modes(K))
+
+
+def srp_fourier_theta(shape, K: int, seed: int, rms: float = 1.0) -> np.ndarray:
+    """Band-limited Gaussian random phase theta (FP64, C-order [z][y][x])."""
+    if isinstance(shape, int):
+        shape = (shape, shape, shape)
+    nz, ny, nx = shape
+    rng = np.random.default_rng(seed)
+    modes = _modes(K)
+    ab = rng.standard_normal((len(modes), 2))
+    hat = np.zeros(shape, dtype=np.complex128)
+    for (kz, ky, kx), (a, b) in zip(modes, ab):
+        hat[kz % nz, ky % ny, kx % nx] += a + 1j * b
+    mirror = np.conj(hat[(-np.arange(nz)) % nz][:, (-np.arange(ny)) % ny][:, :, (-np.arange(nx)) % nx])
+    hat = 0.5 * (hat + mirror)
+    hat[0, 0, 0] = 0.0
+    theta = np.real(np.fft.ifftn(hat))
+    s = math.sqrt(float(np.mean(theta * theta)))
+    if s == 0.0:
+        return theta
+    return theta * (rms / s)
+
+
+# ------------------------------------------------------------------ TG
+def tg_psi(n: int, xi: float, exponent: int) -> np.ndarray:
+    """Taylor-Green ansatz psi_4^exponent on an n^3 grid (complex128)."""
+    x = grid(n)
+    cz = np.cos(x)[:, None, None]
+    cy = np.cos(x)[None, :, None]
+    cx = np.cos(x)[None, None, :]
+    root = np.sqrt(2.0 * np.abs(cz))
+    lam = cx * root
+    mu = cy * root * np.sign(cz)
+    lam, mu = np.broadcast_arrays(lam, mu)
+
+    def psi_e(l, m):
+        r = np.sqrt(l * l + m * m)
+        safe = np.where(r > 0.0, r, 1.0)
+        return np.where(r > 0.0, (l + 1j * m) * np.tanh(r / (math.sqrt(2.0) * xi)) / safe, 0.0)
+
+    s = 1.0 / math.sqrt(2.0)
+    psi4 = psi_e(lam - s, mu) * psi_e(lam, mu - s) * psi_e(lam + s, mu) * psi_e(lam, mu + s)
+    return psi4 ** exponent
+
+
+# ------------------------------------------------------------------ RVR
+PADE_A1 = (73.0 + 3.0 * math.sqrt(201.0)) / 352.0
+PADE_A2 = (6.0 + math.sqrt(201.0)) / 528.0
+PADE_B1 = (21.0 + math.sqrt(201.0)) / 96.0
+
+
+def pade_f(r, xi):
+    """Pade vortex-core profile f(r) (eq. Pade)."""
+    e2 = (np.asarray(r, dtype=np.float64) / xi) ** 2
+    e4 = e2 * e2
+    return np.sqrt((PADE_A1 * e2 + PADE_A2 * e4) / (1.0 + PADE_B1 * e2 + PADE_A2 * e4))
+
+
+def _ring(x, y, z, R, xi):
+    xt, yt, zt = x - math.pi, y - math.pi, z - math.pi
+    rc = np.sqrt(xt * xt + yt * yt)
+    dr = rc - R
+    return pade_f(np.sqrt(dr * dr + zt * zt), xi) * np.exp(1j * np.arctan2(zt, dr))
+
+
+def _pair(x, y, z, R, d, xi):
+    return _ring(x, y, z - 0.5 * d, R, xi) * np.conj(_ring(x, y, z + 0.5 * d, R, xi))
+
+
+def _pair_periodic(x, y, z, R, d, xi):
+    L = TWO_PI
+    out = _pair(x, y, z, R, d, xi)
+    for args in ((2 * L - x, y, z), (-x, y, z), (x, 2 * L - y, z), (x, -y, z),
+                 (x, y, 2 * L - z), (x, y, -z)):
+        out = out * np.conj(_pair(*args, R, d, xi))
+    return out
+
+
+PERMUTATIONS = ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0))
+
+
+def rvr_draws(n_pairs: int, seed: int, rmin: float = 0.3, rmax: float = 0.8):
+    """Per pair, in draw order: R, d = 2R, X, Y, Z, permutation index."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_pairs):
+        R = float(rng.uniform(rmin, rmax))
+        X, Y, Z = (float(v) for v in rng.uniform(0.0, TWO_PI, 3))
+        perm = int(rng.integers(0, 6))
+        out.append({"R": R, "d": 2.0 * R, "X": X, "Y": Y, "Z": Z, "perm": perm})
+    return out
+
+
+def rvr_psi(n: int, xi: float, n_pairs: int, seed: int, rmin=0.3, rmax=0.8) -> np.ndarray:
+    """Product of n_pairs random vortex-ring pairs on an n^3 grid (complex128)."""
+    g = grid(n)
+    coords = (g[None, None, :], g[None, :, None], g[:, None, None])   # x, y, z
+    psi = np.ones((n, n, n), dtype=np.complex128)
+    for p in rvr_draws(n_pairs, seed, rmin, rmax):
+        a = [coords[i] for i in PERMUTATIONS[p["perm"]]]
+        sx = np.mod(a[0] - p["X"], TWO_PI)
+        sy = np.mod(a[1] - p["Y"], TWO_PI)
+        sz = np.mod(a[2] - p["Z"], TWO_PI)
+        sx, sy, sz = np.broadcast_arrays(sx, sy, sz)
+        psi *= _pair_periodic(sx, sy, sz, p["R"], p["d"], xi)
+    return psi
+
+
+# ------------------------------------------------------------------ generic
+def random_field(shape, seed: int, amp_noise: float = 0.3) -> np.ndarray:
+    """Complex test field (1 + amp_noise*g1) exp(i 2 pi u) with seeded white noise."""
+    if isinstance(shape, int):
+        shape = (shape, shape, shape)
+    rng = np.random.default_rng(seed)
+    amp = 1.0 + amp_noise * rng.standard_normal(shape)
+    ph = TWO_PI * rng.random(shape)
+    return amp * np.exp(1j * ph)
+
+
+def random_real(shape, seed: int) -> np.ndarray:
+    if isinstance(shape, int):
+        shape = (shape, shape, shape)
+    return np.random.default_rng(seed).standard_normal(shape)
+
+
+# ------------------------------------------------------------------ workloads
+def alpha_beta_from_xi(xi: float, mach: float = 0.5):
+    """alpha, beta with xi = sqrt(alpha/beta) and alpha beta = 1/(2 M^2)."""
+    ab = 1.0 / (2.0 * mach * mach)
+    alpha = math.sqrt(ab) * xi
+    return alpha, ab / alpha
+
+
+def alpha_beta_table1(n: int):
+    """alpha = 6.4/N, beta = N/3.2 (parameter table of the results section)."""
+    return 6.4 / n, n / 3.2
+
+
+_XI2 = 2.0 * (TWO_PI / 256)
+_XI3 = 3.0 * (TWO_PI / 1024)
+_A2, _B2 = alpha_beta_from_xi(_XI2)
+_A3, _B3 = alpha_beta_from_xi(_XI3)
+
+WORKLOADS = {
+    "srp32": dict(n=32, prec=("c128",), alpha=1.0, beta=1.0, dt=1e-3, steps=200,
+                  ic=("srp", dict(K=4, seed=0)), diag_every=20),
+    "tg256": dict(n=256, prec=("c128", "c64"), alpha=_A2, beta=_B2, dt=5e-4, steps=1000,
+                  ic=("tg", dict(xi=_XI2, exponent=int(math.floor(1.0 / (TWO_PI * _A2))))),
+                  diag_every=100),
+    "rvr1024": dict(n=1024, prec=("c64",), alpha=_A3, beta=_B3, dt=2.5e-4, steps=500,
+                    ic=("rvr", dict(xi=_XI3, n_pairs=40, seed=1)), diag_every=50),
+    "adj128": dict(n=128, prec=("c128",), alpha=0.05, beta=40.0, dt=1e-3, steps=400,
+                   ic=("srp", dict(K=6, seed=2)), ckpt=20, smin=4, smax=12,
+                   fd_h=1e-6, fd_dirs=16, fd_seed0=1000),
+    "ens48": dict(runs=[dict(n=64, alpha=0.1, beta=20.0, seed=100 + i) for i in range(32)]
+                  + [dict(n=96, alpha=6.4 / 96, beta=30.0, seed=132 + i) for i in range(16)],
+                  prec=("c64",), dt=1e-3, steps=300, K=4, diag_every=50),
+}
