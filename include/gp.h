@@ -1,0 +1,189 @@
+/*
+ * gp.h -- C ABI of the MI355X (gfx950) Gross-Pitaevskii split-step library.
+ *
+ * Method: Kobayashi et al., "Quantum turbulence simulations using the
+ * Gross-Pitaevskii equation: high-performance computing and new numerical
+ * benchmarks" (arXiv:2003.03590).  The library integrates the dimensionless GP
+ * equation of the "Scaling and dimensionless equations" section,
+ *
+ *     i d(psi)/dt = ( -alpha lap + beta (|psi|^2 - 1) ) psi        (eq. gpe-num)
+ *
+ * on the periodic box [0, 2 pi)^3 with the second-order Strang/ADI splitting of
+ * the "Numerical method for the time evolution" section (eq. adi_looptime), each
+ * sub-step solved exactly (spectral linear sub-steps, analytic nonlinear phase
+ * rotation), and reports the energy split and shell spectra of the "Energy
+ * decomposition" and "Spectra and structure functions" sections.
+ *
+ * Conventions shared by every entry point
+ *   - Fields are complex, interleaved (re, im), C order [z][y][x] with x
+ *     contiguous: GP_C128 = two doubles (16 B) per point, GP_C64 = two floats
+ *     (8 B).  n[0] = Nx, n[1] = Ny, n[2] = Nz.
+ *   - Pointers marked "dev" are device (HBM) pointers owned by the caller; the
+ *     library never frees them.  Pointers marked "host" are host memory.
+ *   - Every call is asynchronous on the plan's stream unless it returns host
+ *     values, in which case it synchronizes that stream before returning.
+ *   - Every call returns gp_status; nothing throws, exits or prints.  After a
+ *     HIP error the plan is unusable (later calls return GP_ERR_STATE).
+ *   - A plan is not thread-safe; distinct plans are.
+ *   - Supported axis lengths: 1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96,
+ *     128, 192, 256, 384, 512, 768, 1024 (GP_ERR_UNSUPPORTED otherwise).
+ */
+#ifndef GP_H
+#define GP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define GP_API __attribute__((visibility("default")))
+#else
+#define GP_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gp_plan_s gp_plan_t;
+
+typedef enum {
+  GP_OK = 0,
+  GP_ERR_ARG = 1,          /* null pointer, bad size, out-of-range argument */
+  GP_ERR_UNSUPPORTED = 2,  /* axis length or precision not compiled */
+  GP_ERR_HIP = 3,          /* a HIP runtime call failed; the plan is now unusable */
+  GP_ERR_NOMEM = 4,        /* device or pinned allocation failed */
+  GP_ERR_NONFINITE = 5,    /* a diagnostic is NaN/Inf (values are still written) */
+  GP_ERR_STATE = 6         /* plan unusable after an earlier HIP error, or wrong plan kind */
+} gp_status;
+
+typedef enum { GP_C128 = 0, GP_C64 = 1 } gp_prec;
+
+/* Problem description (paper scaling: L = 2 pi, coefficients alpha and beta of
+ * eq. gpe-num, time step dt). */
+typedef struct {
+  int32_t n[3];      /* grid points along x, y, z */
+  double alpha;      /* coefficient of -lap */
+  double beta;       /* coefficient of (|psi|^2 - 1) */
+  double dt;         /* time step of gp_step_n */
+  int32_t prec;      /* gp_prec: storage and transform precision */
+  uint32_t flags;    /* reserved, must be 0 */
+} gp_desc;
+
+/* Energies per unit volume in the paper's scaling:
+ *   mass     N = <|psi|^2>                                   (eq. scaling-N)
+ *   energy   E = 2 alpha^2 sum_k |k|^2 |c_k|^2 + alpha beta <(|psi|^2-1)^2>
+ *                                                            (eq. scaling-energy)
+ *   e_kin    <|w|^2>/2, w = 2 alpha Im(conj(psi) grad psi)/|psi| = sqrt(rho) v
+ *   e_kin_i, e_kin_c   incompressible / compressible parts of e_kin (Helmholtz
+ *            split of w; the k = 0 mode counts as incompressible)
+ *   e_q      2 alpha^2 <|grad |psi||^2>   e_int  alpha beta <(|psi|^2-1)^2>
+ *                                            (eq. scaling-energy-mod-rho)        */
+typedef struct {
+  double mass, energy, e_kin, e_kin_i, e_kin_c, e_q, e_int;
+} gp_energy;
+
+/* Create a plan for one grid.  Generates the FP64 twiddle and propagator
+ * tables on the host (rounded to the working precision) and uploads them;
+ * selects the compiled FFT schedule of each axis.  hip_stream: a hipStream_t,
+ * or NULL for the default stream.  *out receives the plan (NULL on error). */
+GP_API gp_status gp_plan(const gp_desc* d, void* hip_stream, gp_plan_t** out);
+
+/* Create a plan for an ensemble of independent runs (grid sizes may differ;
+ * all runs share one precision).  Runs are advanced together by
+ * gp_step_n_batch, which groups runs of equal size into single launches and
+ * records the whole sequence of launches as one HIP graph. */
+GP_API gp_status gp_plan_batch(const gp_desc* runs, int32_t nruns, void* hip_stream, gp_plan_t** out);
+
+GP_API gp_status gp_plan_destroy(gp_plan_t* p);
+
+/* Bytes of one state (N^3 * S) -- for a batch plan, of run i (i < nruns). */
+GP_API size_t gp_state_bytes(const gp_plan_t* p, int32_t run);
+/* Bytes of the caller-provided diagnostics workspace (5 states). */
+GP_API size_t gp_work_bytes(const gp_plan_t* p);
+/* Number of integer shells s = round(|k|) of the spectra. */
+GP_API int32_t gp_nshell(const gp_plan_t* p);
+
+/* psi = exp(i theta) pointwise (initial condition of the smoothed-random-phase
+ * construction, eq. SRP_Init).  theta: dev, N^3 doubles; psi: dev, out. */
+GP_API gp_status gp_init_phase(gp_plan_t* p, const double* theta, void* psi);
+
+/* One directional linear sub-step S(s, L_axis) psi = F_j^-1 exp(-i alpha k_j^2 s) F_j psi,
+ * in place (time-evolution section).  axis: 0 = x, 1 = y, 2 = z. */
+GP_API gp_status gp_substep_linear(gp_plan_t* p, void* psi, int32_t axis, double s);
+
+/* Nonlinear sub-step S(s, N) psi = exp(-i beta (|psi|^2 - 1) s) psi, in place. */
+GP_API gp_status gp_substep_nonlinear(gp_plan_t* p, void* psi, double s);
+
+/* nsteps Strang steps of dt (nsteps < 0: |nsteps| steps of -dt), in place:
+ * psi <- [L(dt/2) N(dt) L(dt/2)]^n psi with L = L_x L_y L_z (eq. adi_looptime).
+ * Adjacent half steps are merged and the nonlinear rotation is fused into the
+ * following x pass: 3 (|n| + 1) axis passes, each reading and writing psi once. */
+GP_API gp_status gp_step_n(gp_plan_t* p, void* psi, int64_t nsteps);
+
+/* The same steps in the literal 3-D form: 3-D FFT, multiply by
+ * exp(-i alpha |k|^2 dt/2), inverse 3-D FFT, nonlinear rotation, and again
+ * (the wording of the spectral sub-step).  About 3x the HBM traffic of gp_step_n. */
+GP_API gp_status gp_step_literal_n(gp_plan_t* p, void* psi, int64_t nsteps);
+
+/* 3-D transform: dir = -1 forward with 1/N^3 (c_k = N^-3 sum_x psi e^{-ik.x}),
+ * dir = +1 inverse without factor.  Natural fftfreq order of k.  in may equal out. */
+GP_API gp_status gp_fft3(gp_plan_t* p, const void* in, void* out, int32_t dir);
+
+/* Mass, energy and its decomposition (see gp_energy).  work: dev, gp_work_bytes.
+ * Synchronizes.  GP_ERR_NONFINITE if any value is NaN/Inf. */
+GP_API gp_status gp_energies(gp_plan_t* p, const void* psi, void* work, gp_energy* out);
+
+/* Shell spectra (spectra section, Parseval per unit volume): out is host
+ * [4][nshell] doubles, rows E_kin^i(s), E_kin^c(s), E_q(s), E_int(s), each summing
+ * to its energy.  energies (host, may be NULL) receives gp_energy of the same
+ * evaluation.  nshell must equal gp_nshell.  Synchronizes. */
+GP_API gp_status gp_spectra(gp_plan_t* p, const void* psi, void* work, double* out, int32_t nshell,
+                     gp_energy* energies);
+
+/* Second-order structure function of rho = |psi|^2 (eq. strfunc-def with v -> rho,
+ * spatial mean, averaged over the three axes): out is host, Nx/2 doubles for lags
+ * m = 1 .. Nx/2 (cubic grids only).  p_order must be 2.  Synchronizes. */
+GP_API gp_status gp_structure_fn(gp_plan_t* p, const void* psi, void* work, int32_t p_order, double* out);
+
+/* Loss J = 1/2 sum over shells smin..smax of |w^i_k|^2 (incompressible kinetic
+ * energy spectrum summed over those shells) and its gradient lam (dev, out) with
+ * dJ = Re sum conj(lam) dpsi.  J: host.  Synchronizes. */
+GP_API gp_status gp_loss_ekin_i_shells(gp_plan_t* p, const void* psi, void* work, int32_t smin,
+                                int32_t smax, double* J, void* lam);
+
+/* Adjoint of nsteps Strang steps from psi_seg_start: recomputes the forward
+ * states phi_n = L(dt/2) psi_n of the segment into tape (dev, nsteps states),
+ * then lam <- [L(-dt/2) N'(phi_n)^dagger L(-dt/2)] ... lam for n = nsteps-1 .. 0
+ * (conjugate propagators in reverse order and the adjoint of the linearised
+ * nonlinear rotation).  lam: dev, in/out.  GP_C128 only. */
+GP_API gp_status gp_adjoint_step_n(gp_plan_t* p, const void* psi_seg_start, void* lam, int64_t nsteps,
+                            void* tape);
+
+/* dJ/dtheta = Im(lam0 conj(psi0)) for psi0 = exp(i theta).  dJ_dtheta: dev, N^3 doubles. */
+GP_API gp_status gp_phase_grad(gp_plan_t* p, const void* psi0, const void* lam0, double* dJ_dtheta);
+
+/* Ensemble: advance run i's state psis[i] (host array of dev pointers) by nsteps.
+ * The first call for a given set of pointers and nsteps records a HIP graph;
+ * later identical calls replay it. */
+GP_API gp_status gp_step_n_batch(gp_plan_t* p, void* const* psis, int64_t nsteps);
+
+/* Ensemble: mass and energy of every run (host out, 2 * nruns doubles:
+ * mass_i, energy_i).  work: dev, gp_work_bytes.  Synchronizes. */
+GP_API gp_status gp_energies_batch(gp_plan_t* p, void* const* psis, void* work, double* out);
+
+/* Message of the last non-OK status on this thread ("" if none). */
+GP_API const char* gp_last_error(void);
+
+/* Name of the compiled FFT schedule used for an axis, e.g. "N=256 T=16 W=8 R=16x16". */
+GP_API const char* gp_schedule_name(const gp_plan_t* p, int32_t axis);
+
+/* Number of compiled schedule variants for an axis length and precision, and
+ * selection of one of them for an axis of a plan (autotuning). */
+GP_API int32_t gp_variant_count(int32_t n, int32_t prec);
+GP_API gp_status gp_select_variant(gp_plan_t* p, int32_t axis, int32_t variant);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GP_H */

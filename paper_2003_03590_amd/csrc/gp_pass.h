@@ -1,0 +1,346 @@
+// Axis-pass kernel: the directional spectral sub-step of the split step.
+//
+// One launch processes every pencil of the grid along one axis j and applies
+//   PROP: v <- F_j^-1 ( m(k_j) * F_j v )         (S(s, L_j) with m = exp(-i alpha k_j^2 s)/N_j,
+//                                                  or a spectral derivative with m = i k_j / N_j)
+//   FWD : v <- scale * F_j v        (natural frequency order out)
+//   INV : v <- scale * F_j^-1 v     (natural frequency order in, unnormalised inverse)
+// with optional pointwise prologues (the nonlinear sub-step S(dt, N), its adjoint, the
+// density rho - 1) fused in front of the transform.
+//
+// Transform structure (time-evolution section: each S(s, L_j) is exact in Fourier space):
+// N = R_0 R_1 ... R_{S-1}; T threads per pencil each hold E = N/T points in registers.
+// Forward stages are decimation-in-frequency butterflies done in registers, with an
+// LDS exchange between stages; after the last stage position p holds the coefficient
+// of the digit-reversed frequency.  PROP multiplies there by a table already stored in
+// position order and runs the exact inverse (conjugate-twiddle DIT) stages in reverse, so
+// no reordering pass is ever needed.  W pencils share one workgroup; for the strided
+// axes (y, z) the W pencils are x-adjacent so each global access is a W*S-byte row.
+#pragma once
+
+#include "gp_device.h"
+
+namespace gpk {
+
+enum PassKind { CONTIG = 0, STRIDED = 1 };
+enum PassMode { PROP = 0, FWD = 1, INV = 2 };
+// pointwise work fused in front of the transform (PRO_KIN: none, but accumulate
+// sum k_j^2 |F_j v|^2 after the forward transform for the kinetic energy)
+enum Prologue { PRO_NONE = 0, PRO_NL = 1, PRO_ADJ_NL = 2, PRO_DENSITY = 3, PRO_KIN = 4 };
+
+// per-run pointers of a grouped (ensemble) launch: run = blockIdx.y
+struct RunPtrs {
+  const void* in;
+  void* out;
+  const void* mult;
+  double nl_coef;
+};
+
+struct PassArgs {
+  const RunPtrs* batch;    // grouped launch over runs of one size, or null
+  const void* in;          // input field (complex, working precision)
+  void* out;               // output field (may equal in)
+  const void* mult;        // PROP: multiplier in position order (N_j complex)
+  const void* tw;          // W_N^m = exp(-2 pi i m / N_j), m < N_j
+  const void* aux;         // PRO_ADJ_NL: forward state phi at the same points
+  const void* pmx;         // optional per-pencil factors (natural order along x, y) for the
+  const void* pmy;         //   literal 3-D propagator on the z pass; null otherwise
+  const double* ksq;       // k_j^2 in position order (kinetic accumulation)
+  double* kin_partial;     // per-workgroup partial sum of k_j^2 |F_j v|^2 (or null)
+  double nl_coef;          // beta * dt of the nonlinear prologue
+  double scale;            // FWD/INV output scale
+  long npencils;           // number of pencils along this axis
+  long inner, outer;       // pencil p starts at (p / inner) * outer + (p % inner)
+  long es;                 // element stride along the axis
+  int nx;                  // grid size along x (pencil factor lookup on the z pass)
+};
+
+template <int N_, int T_, int W_, int R0, int R1, int R2>
+struct Sched {
+  static constexpr int N = N_, T = T_, W = W_, E = N_ / T_;
+  static constexpr int NS = (R0 > 1) + (R1 > 1) + (R2 > 1);
+  static constexpr int rad(int s) { return s == 0 ? R0 : s == 1 ? R1 : R2; }
+  // product of the radices after stage s (the digit weight of stage s)
+  static constexpr int M(int s) { int m = 1; for (int i = s + 1; i < NS; ++i) m *= rad(i); return m; }
+  // product of the radices before stage s (the frequency weight of stage s)
+  static constexpr int K(int s) { int k = 1; for (int i = 0; i < s; ++i) k *= rad(i); return k; }
+  static constexpr bool valid() {
+    if (T * E != N) return false;
+    int p = 1;
+    for (int s = 0; s < NS; ++s) { if (E % rad(s)) return false; p *= rad(s); }
+    return p == N;
+  }
+  static_assert(valid(), "inconsistent FFT schedule");
+  static constexpr int THREADS = T * W;
+  // LDS layout: CONTIG [col][pos + pad], STRIDED [pos][col]
+  static constexpr int CPAD = N + N / 16;
+  static constexpr int LDS_ELEMS = (NS > 1) ? W * CPAD : 1;
+};
+
+// position held by register (j + B*r) of thread t at stage s
+template <class S, int s>
+__device__ __forceinline__ int stage_pos(int t, int j, int r) {
+  constexpr int Ms = S::M(s);
+  constexpr int Ls = S::rad(s) * Ms;
+  const int g = t + S::T * j;
+  return (g / Ms) * Ls + r * Ms + (g % Ms);
+}
+
+// position of natural frequency k (digit-reversal of the DIF output order)
+template <class S>
+__device__ __forceinline__ int freq_pos(int k) {
+  int p = 0;
+#pragma unroll
+  for (int s = 0; s < S::NS; ++s) p += ((k / S::K(s)) % S::rad(s)) * S::M(s);
+  return p;
+}
+
+template <class S, int KIND>
+__device__ __forceinline__ int lds_addr(int pos, int col) {
+  if constexpr (KIND == CONTIG) return col * S::CPAD + pos + (pos >> 4);
+  else return pos * S::W + col;
+}
+
+// layout ids for exchanges: 0..NS-1 = stage layouts, -1 = natural frequency layout
+template <class Real, class S, int KIND, int L>
+__device__ __forceinline__ void put(cplx<Real>* lds, const cplx<Real>* v, int t, int col) {
+  if constexpr (L < 0) {
+#pragma unroll
+    for (int e = 0; e < S::E; ++e) lds[lds_addr<S, KIND>(freq_pos<S>(t + S::T * e), col)] = v[e];
+  } else {
+    constexpr int B = S::E / S::rad(L);
+#pragma unroll
+    for (int r = 0; r < S::rad(L); ++r)
+#pragma unroll
+      for (int j = 0; j < B; ++j) lds[lds_addr<S, KIND>(stage_pos<S, L>(t, j, r), col)] = v[j + B * r];
+  }
+}
+template <class Real, class S, int KIND, int L>
+__device__ __forceinline__ void get(const cplx<Real>* lds, cplx<Real>* v, int t, int col) {
+  if constexpr (L < 0) {
+#pragma unroll
+    for (int e = 0; e < S::E; ++e) v[e] = lds[lds_addr<S, KIND>(freq_pos<S>(t + S::T * e), col)];
+  } else {
+    constexpr int B = S::E / S::rad(L);
+#pragma unroll
+    for (int r = 0; r < S::rad(L); ++r)
+#pragma unroll
+      for (int j = 0; j < B; ++j) v[j + B * r] = lds[lds_addr<S, KIND>(stage_pos<S, L>(t, j, r), col)];
+  }
+}
+
+template <class Real, class S, int KIND, int FROM, int TO>
+__device__ __forceinline__ void exchange(cplx<Real>* lds, cplx<Real>* v, int t, int col) {
+  __syncthreads();                          // previous readers of lds are done
+  put<Real, S, KIND, FROM>(lds, v, t, col);
+  __syncthreads();
+  get<Real, S, KIND, TO>(lds, v, t, col);
+}
+
+// forward DIF stage s: butterfly over digit s, then twiddle W_{L_s}^{lo*k}
+template <class Real, class S, int s>
+__device__ __forceinline__ void fwd_stage(cplx<Real>* v, int t, const cplx<Real>* __restrict__ tw) {
+  constexpr int R = S::rad(s), B = S::E / R, Ms = S::M(s), Ls = R * Ms, STEP = S::N / Ls;
+#pragma unroll
+  for (int j = 0; j < B; ++j) {
+    cplx<Real> x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[r] = v[j + B * r];
+    Dft<R, -1, Real>::run(x);
+    if constexpr (Ms > 1) {
+      const int lo = (t + S::T * j) % Ms;
+#pragma unroll
+      for (int k = 1; k < R; ++k) x[k] = cmul(x[k], tw[lo * k * STEP]);
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) v[j + B * k] = x[k];
+  }
+}
+
+// inverse of fwd_stage (up to the factor R): conjugate twiddle, then inverse butterfly
+template <class Real, class S, int s>
+__device__ __forceinline__ void inv_stage(cplx<Real>* v, int t, const cplx<Real>* __restrict__ tw) {
+  constexpr int R = S::rad(s), B = S::E / R, Ms = S::M(s), Ls = R * Ms, STEP = S::N / Ls;
+#pragma unroll
+  for (int j = 0; j < B; ++j) {
+    cplx<Real> x[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) x[k] = v[j + B * k];
+    if constexpr (Ms > 1) {
+      const int lo = (t + S::T * j) % Ms;
+#pragma unroll
+      for (int k = 1; k < R; ++k) x[k] = cmulc(x[k], tw[lo * k * STEP]);
+    }
+    Dft<R, +1, Real>::run(x);
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[j + B * r] = x[r];
+  }
+}
+
+template <class Real, class S, int KIND, int s>
+__device__ __forceinline__ void forward_all(cplx<Real>* v, cplx<Real>* lds, int t, int col,
+                                            const cplx<Real>* __restrict__ tw) {
+  fwd_stage<Real, S, s>(v, t, tw);
+  if constexpr (s + 1 < S::NS) {
+    exchange<Real, S, KIND, s, s + 1>(lds, v, t, col);
+    forward_all<Real, S, KIND, s + 1>(v, lds, t, col, tw);
+  }
+}
+
+template <class Real, class S, int KIND, int s>
+__device__ __forceinline__ void inverse_all(cplx<Real>* v, cplx<Real>* lds, int t, int col,
+                                            const cplx<Real>* __restrict__ tw) {
+  inv_stage<Real, S, s>(v, t, tw);
+  if constexpr (s > 0) {
+    exchange<Real, S, KIND, s, s - 1>(lds, v, t, col);
+    inverse_all<Real, S, KIND, s - 1>(v, lds, t, col, tw);
+  }
+}
+
+// nonlinear sub-step S(dt, N): v <- v exp(-i beta (|v|^2 - 1) dt)
+template <class Real>
+__device__ __forceinline__ cplx<Real> nl_rotate(cplx<Real> v, Real coef) {
+  Real s, c;
+  sincos_rot(-coef * (cabs2(v) - Real(1)), &s, &c);
+  return cmul(v, mk(c, s));
+}
+
+// adjoint of the linearised nonlinear sub-step at phi:
+//   lam <- conj(u) lam + 2 beta dt Im(conj(lam) u phi) phi,  u = exp(-i beta (|phi|^2-1) dt)
+template <class Real>
+__device__ __forceinline__ cplx<Real> nl_adjoint(cplx<Real> lam, cplx<Real> phi, Real coef) {
+  Real s, c;
+  sincos_rot(-coef * (cabs2(phi) - Real(1)), &s, &c);
+  const cplx<Real> u = mk(c, s);
+  const cplx<Real> up = cmul(u, phi);
+  const Real im = lam.x * up.y - lam.y * up.x;          // Im(conj(lam) * up)
+  const cplx<Real> r = cmulc(lam, u);                    // conj(u) lam
+  const Real f = Real(2) * coef * im;
+  return mk(r.x + f * phi.x, r.y + f * phi.y);
+}
+
+template <class Real, class S, int KIND, int MODE, int PRO>
+__global__ __launch_bounds__(S::THREADS) void axis_pass(PassArgs a) {
+  using C = cplx<Real>;
+  constexpr int T = S::T, W = S::W, E = S::E;
+  __shared__ C lds[S::LDS_ELEMS];
+  __shared__ double red[S::THREADS / 64 + 1];
+
+  if (a.batch) {                          // uniform per workgroup
+    const RunPtrs r = a.batch[blockIdx.y];
+    a.in = r.in; a.out = r.out; a.mult = r.mult; a.nl_coef = r.nl_coef;
+  }
+  const int tid = threadIdx.x;
+  int t, col;
+  if constexpr (KIND == CONTIG) { t = tid % T; col = tid / T; }
+  else { col = tid % W; t = tid / W; }
+  const long p = (long)blockIdx.x * W + col;
+  const bool active = p < a.npencils;
+  const long pp = active ? p : 0;
+  const long base = (pp / a.inner) * a.outer + (pp % a.inner);
+  const long es = a.es;
+  const C* __restrict__ in = reinterpret_cast<const C*>(a.in);
+  C* __restrict__ out = reinterpret_cast<C*>(a.out);
+  const C* __restrict__ tw = reinterpret_cast<const C*>(a.tw);
+
+  C v[E];
+  if (active) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = in[base + (long)(t + T * e) * es];
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = mk(Real(0), Real(0));
+  }
+
+  if constexpr (MODE != INV) {
+    if constexpr (PRO == PRO_NL) {
+      const Real coef = Real(a.nl_coef);
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = nl_rotate(v[e], coef);
+    } else if constexpr (PRO == PRO_ADJ_NL) {
+      const C* __restrict__ phi = reinterpret_cast<const C*>(a.aux);
+      const Real coef = Real(a.nl_coef);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const C f = active ? phi[base + (long)(t + T * e) * es] : mk(Real(0), Real(0));
+        v[e] = nl_adjoint(v[e], f, coef);
+      }
+    } else if constexpr (PRO == PRO_DENSITY) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = mk(cabs2(v[e]) - Real(1), Real(0));
+    }
+  }
+
+  if constexpr (MODE == INV) {
+    if constexpr (S::NS > 1) exchange<Real, S, KIND, -1, S::NS - 1>(lds, v, t, col);
+    inverse_all<Real, S, KIND, S::NS - 1>(v, lds, t, col, tw);
+    const Real sc = Real(a.scale);
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = cscale(v[e], sc);
+  } else {
+    forward_all<Real, S, KIND, 0>(v, lds, t, col, tw);
+    constexpr int L = S::NS - 1;
+    constexpr int B = E / S::rad(L);
+    if constexpr (MODE == PROP) {
+      if constexpr (PRO == PRO_KIN) {
+        double acc = 0.0;
+#pragma unroll
+        for (int r = 0; r < S::rad(L); ++r)
+#pragma unroll
+          for (int j = 0; j < B; ++j) {
+            const int pos = stage_pos<S, L>(t, j, r);
+            const C x = v[j + B * r];
+            acc += a.ksq[pos] * ((double)x.x * x.x + (double)x.y * x.y);
+          }
+        if (!active) acc = 0.0;
+        // fixed-order reduction: wave butterfly, then waves in order
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if ((tid & 63) == 0) red[tid >> 6] = acc;
+        __syncthreads();
+        if (tid == 0) {
+          double s = 0.0;
+          for (int w = 0; w < S::THREADS / 64 + (S::THREADS % 64 ? 1 : 0); ++w) s += red[w];
+          a.kin_partial[blockIdx.x] = s;
+        }
+      }
+      const C* __restrict__ mult = reinterpret_cast<const C*>(a.mult);
+      C pf = mk(Real(1), Real(0));
+      if (a.pmx) {
+        const long xi = pp % a.nx, yi = pp / a.nx;
+        pf = cmul(reinterpret_cast<const C*>(a.pmx)[xi], reinterpret_cast<const C*>(a.pmy)[yi]);
+      }
+#pragma unroll
+      for (int r = 0; r < S::rad(L); ++r)
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+          const int pos = stage_pos<S, L>(t, j, r);
+          v[j + B * r] = cmul(v[j + B * r], cmul(mult[pos], pf));
+        }
+      inverse_all<Real, S, KIND, L>(v, lds, t, col, tw);
+    } else {  // FWD: reorder to natural frequency order
+      if constexpr (S::NS > 1) exchange<Real, S, KIND, L, -1>(lds, v, t, col);
+      const Real sc = Real(a.scale);
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = cscale(v[e], sc);
+    }
+  }
+
+  if (active) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) out[base + (long)(t + T * e) * es] = v[e];
+  }
+}
+
+// launcher signature shared by every instantiation
+using PassLauncher = void (*)(const PassArgs&, unsigned grid, unsigned runs, hipStream_t stream);
+
+template <class Real, class S, int KIND, int MODE, int PRO>
+void launch_pass(const PassArgs& a, unsigned grid, unsigned runs, hipStream_t stream) {
+  hipLaunchKernelGGL((axis_pass<Real, S, KIND, MODE, PRO>), dim3(grid, runs), dim3(S::THREADS), 0, stream, a);
+}
+
+// kernel variants compiled for every schedule
+enum Variant { V_PROP = 0, V_PROP_NL, V_PROP_ADJ, V_PROP_KIN, V_FWD, V_FWD_DENSITY, V_INV, V_COUNT };
+
+}  // namespace gpk

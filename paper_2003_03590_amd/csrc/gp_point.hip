@@ -1,0 +1,493 @@
+// Pointwise and reduction kernels of the Gross-Pitaevskii library:
+// the initial phase field, the standalone nonlinear sub-step, the
+// hydrodynamic diagnostics (energy decomposition and shell spectra), the
+// spectral loss and its gradient, the phase gradient, and the density
+// structure function.  All reductions are deterministic: fixed-order wave
+// butterflies, per-workgroup partials, and a fixed-order final sum with
+// Neumaier compensation; shell bins are accumulated per wavefront in LDS.
+#include "gp_point.h"
+
+namespace gpk {
+
+// ----------------------------------------------------------------- helpers
+struct Neu {          // Neumaier compensated sum
+  double s = 0.0, c = 0.0;
+  __device__ __forceinline__ void add(double x) {
+    const double t = s + x;
+    c += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
+    s = t;
+  }
+  __device__ __forceinline__ double val() const { return s + c; }
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// block of 256 threads: sum of v in a fixed order, result valid in thread 0
+__device__ __forceinline__ double block_sum256(double v, double* sh) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = ((sh[0] + sh[1]) + (sh[2] + sh[3]));
+  return r;
+}
+
+template <class Real>
+__device__ __forceinline__ cplx<Real> ldc(const void* p, long i) { return reinterpret_cast<const cplx<Real>*>(p)[i]; }
+template <class Real>
+__device__ __forceinline__ void stc(void* p, long i, double re, double im) {
+  reinterpret_cast<cplx<Real>*>(p)[i] = mk(Real(re), Real(im));
+}
+
+// integer shell s = round(|k|): (2s-1)^2 <= 4|k|^2 < (2s+1)^2
+__device__ __forceinline__ int shell_of(long k2) {
+  const long q = 4 * k2;
+  long r = (long)sqrt((double)q);
+  while (r * r > q) --r;
+  while ((r + 1) * (r + 1) <= q) ++r;
+  return (int)((r + 1) / 2);
+}
+
+__device__ __forceinline__ int kfreq(int i, int n) { return (2 * i < n) ? i : i - n; }  // fftfreq (Nyquist -> -n/2)
+__device__ __forceinline__ int kfirst(int i, int n) {                                   // Nyquist zeroed
+  return (n % 2 == 0 && 2 * i == n) ? 0 : kfreq(i, n);
+}
+
+// ----------------------------------------------------------------- elementwise
+template <class Real>
+__global__ void k_init_phase(const double* __restrict__ theta, void* psi, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    double s, c;
+    sincos(theta[i], &s, &c);
+    stc<Real>(psi, i, c, s);
+  }
+}
+
+template <class Real>
+__global__ void k_nonlinear(void* psi, long n, double coef) {
+  cplx<Real>* p = reinterpret_cast<cplx<Real>*>(psi);
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const cplx<Real> v = p[i];
+    Real s, c;
+    sincos_rot(Real(-coef) * (cabs2(v) - Real(1)), &s, &c);
+    p[i] = cmul(v, mk(c, s));
+  }
+}
+
+template <class Real>
+__global__ void k_scale_copy(const void* in, void* out, long n, double scale) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const cplx<Real> v = ldc<Real>(in, i);
+    stc<Real>(out, i, (double)v.x * scale, (double)v.y * scale);
+  }
+}
+
+// multiply by the separable 3-D propagator mx[kx] my[ky] mz[kz] (natural order tables)
+template <class Real>
+__global__ void k_mult3(void* f, int nx, int ny, int nz, const void* mx, const void* my, const void* mz) {
+  const long n = (long)nx * ny * nz;
+  cplx<Real>* p = reinterpret_cast<cplx<Real>*>(f);
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const int ix = (int)(i % nx), iy = (int)((i / nx) % ny), iz = (int)(i / ((long)nx * ny));
+    const cplx<Real> m = cmul(cmul(ldc<Real>(mx, ix), ldc<Real>(my, iy)), ldc<Real>(mz, iz));
+    p[i] = cmul(p[i], m);
+  }
+}
+
+// ----------------------------------------------------------------- diagnostics
+// In: psi and its spectral derivatives d0 = d/dx, d1 = d/dy, d2 = d/dz (in f0, f1, f2).
+// Out (in place): f0 = w_x + i w_y, f1 = w_z + i |psi|, f2 = (|psi|^2 - 1) + 0i,
+// w = 2 alpha Im(conj(psi) grad psi)/|psi| (0 where psi = 0).
+// Partials per block: [sum rho, sum (rho-1)^2, sum |w|^2].
+template <class Real>
+__global__ __launch_bounds__(256) void k_diag_fields(const void* psi, void* f0, void* f1, void* f2, long n,
+                                                     double alpha, double* __restrict__ partial) {
+  __shared__ double sh[4];
+  Neu a0, a1, a2;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+    const cplx<Real> p = ldc<Real>(psi, i);
+    const cplx<Real> dx = ldc<Real>(f0, i), dy = ldc<Real>(f1, i), dz = ldc<Real>(f2, i);
+    const double pr = p.x, pi = p.y;
+    const double rho = pr * pr + pi * pi;
+    const double amp = sqrt(rho);
+    double wx = 0, wy = 0, wz = 0;
+    if (amp > 0.0) {
+      const double f = 2.0 * alpha / amp;
+      wx = f * (pr * (double)dx.y - pi * (double)dx.x);
+      wy = f * (pr * (double)dy.y - pi * (double)dy.x);
+      wz = f * (pr * (double)dz.y - pi * (double)dz.x);
+    }
+    stc<Real>(f0, i, wx, wy);
+    stc<Real>(f1, i, wz, amp);
+    stc<Real>(f2, i, rho - 1.0, 0.0);
+    a0.add(rho);
+    a1.add((rho - 1.0) * (rho - 1.0));
+    a2.add(wx * wx + wy * wy + wz * wz);
+  }
+  const double s0 = block_sum256(a0.val(), sh);
+  const double s1 = block_sum256(a1.val(), sh);
+  const double s2 = block_sum256(a2.val(), sh);
+  if (threadIdx.x == 0) {
+    partial[3 * blockIdx.x + 0] = s0;
+    partial[3 * blockIdx.x + 1] = s1;
+    partial[3 * blockIdx.x + 2] = s2;
+  }
+}
+
+// Shell binning of the hydrodynamic spectra.  F0 = FFT(w_x + i w_y),
+// F1 = FFT(w_z + i |psi|), F2 = FFT(rho - 1) (unnormalised, natural order).
+// Per k: unpack the real-field transforms with the mirror -k, normalise by
+// 1/Ntot, split w into compressible (parallel to k) and incompressible parts,
+// and add 1/2|w^i|^2, 1/2|w^c|^2, 2 alpha^2 |k~|^2 |a|^2, alpha beta |b|^2 to
+// shell round(|k|).  One wavefront per workgroup; bins live in LDS.
+template <class Real>
+__global__ __launch_bounds__(64) void k_spectral(const void* F0, const void* F1, const void* F2, int nx, int ny,
+                                                 int nz, double alpha, double beta, int nshell, long chunk,
+                                                 double* __restrict__ bins_partial) {
+  extern __shared__ double bins[];            // [4][nshell]
+  for (int i = threadIdx.x; i < 4 * nshell; i += 64) bins[i] = 0.0;
+  __syncthreads();
+  const long n = (long)nx * ny * nz;
+  const double inv = 1.0 / (double)n;
+  const long i0 = (long)blockIdx.x * chunk;
+  const long i1 = (i0 + chunk < n) ? i0 + chunk : n;
+  for (long i = i0 + threadIdx.x; i < i1; i += 64) {
+    const int ix = (int)(i % nx), iy = (int)((i / nx) % ny), iz = (int)(i / ((long)nx * ny));
+    const long m = (long)((nz - iz) % nz) * nx * ny + (long)((ny - iy) % ny) * nx + (nx - ix) % nx;
+    const cplx<Real> z0 = ldc<Real>(F0, i), z0m = ldc<Real>(F0, m);
+    const cplx<Real> z1 = ldc<Real>(F1, i), z1m = ldc<Real>(F1, m);
+    const cplx<Real> z2 = ldc<Real>(F2, i), z2m = ldc<Real>(F2, m);
+    // A = (Z + conj Zm)/2, B = (Z - conj Zm)/(2i)
+    const double wxr = 0.5 * ((double)z0.x + z0m.x) * inv, wxi = 0.5 * ((double)z0.y - z0m.y) * inv;
+    const double wyr = 0.5 * ((double)z0.y + z0m.y) * inv, wyi = -0.5 * ((double)z0.x - z0m.x) * inv;
+    const double wzr = 0.5 * ((double)z1.x + z1m.x) * inv, wzi = 0.5 * ((double)z1.y - z1m.y) * inv;
+    const double ar = 0.5 * ((double)z1.y + z1m.y) * inv, ai = -0.5 * ((double)z1.x - z1m.x) * inv;
+    const double br = 0.5 * ((double)z2.x + z2m.x) * inv, bi = 0.5 * ((double)z2.y - z2m.y) * inv;
+    const int kx = kfreq(ix, nx), ky = kfreq(iy, ny), kz = kfreq(iz, nz);
+    const long k2 = (long)kx * kx + (long)ky * ky + (long)kz * kz;
+    double cr = 0, ci = 0;
+    if (k2 > 0) {
+      const double kdr = kx * wxr + ky * wyr + kz * wzr, kdi = kx * wxi + ky * wyi + kz * wzi;
+      cr = kdr / (double)k2; ci = kdi / (double)k2;
+    }
+    const double cxr = kx * cr, cxi = kx * ci, cyr = ky * cr, cyi = ky * ci, czr = kz * cr, czi = kz * ci;
+    const double ec = 0.5 * (cxr * cxr + cxi * cxi + cyr * cyr + cyi * cyi + czr * czr + czi * czi);
+    const double ixr = wxr - cxr, ixi = wxi - cxi, iyr = wyr - cyr, iyi = wyi - cyi, izr = wzr - czr, izi = wzi - czi;
+    const double ei = 0.5 * (ixr * ixr + ixi * ixi + iyr * iyr + iyi * iyi + izr * izr + izi * izi);
+    const int fx = kfirst(ix, nx), fy = kfirst(iy, ny), fz = kfirst(iz, nz);
+    const double eq = 2.0 * alpha * alpha * (double)((long)fx * fx + (long)fy * fy + (long)fz * fz) * (ar * ar + ai * ai);
+    const double eint = alpha * beta * (br * br + bi * bi);
+    const int s = shell_of(k2);
+    atomicAdd(&bins[s], ei);
+    atomicAdd(&bins[nshell + s], ec);
+    atomicAdd(&bins[2 * nshell + s], eq);
+    atomicAdd(&bins[3 * nshell + s], eint);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 4 * nshell; i += 64) bins_partial[(long)blockIdx.x * 4 * nshell + i] = bins[i];
+}
+
+// Final fixed-order reduction of every diagnostic partial (one block of 256).
+// out[0..6] = gp_energy, out[7 ..] = spectra [4][nshell].
+__global__ __launch_bounds__(256) void k_finalize_diag(const double* __restrict__ kin, int nkin0, int nkin1, int nkin2,
+                                                       double kin_w0, double kin_w1, double kin_w2,
+                                                       const double* __restrict__ field, int nfield,
+                                                       const double* __restrict__ bins, int nbins, int nshell,
+                                                       double alpha, double beta, double ntot, double* __restrict__ out) {
+  extern __shared__ double spec[];            // [4][nshell]
+  // spectra: one thread per (row, shell), blocks summed in order
+  for (int q = threadIdx.x; q < 4 * nshell; q += 256) {
+    Neu a;
+    for (int b = 0; b < nbins; ++b) a.add(bins[(long)b * 4 * nshell + q]);
+    spec[q] = a.val();
+    out[7 + q] = spec[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Neu k0, k1, k2, f0, f1, f2, ei, ec, eq;
+    for (int b = 0; b < nkin0; ++b) k0.add(kin[b]);
+    for (int b = 0; b < nkin1; ++b) k1.add(kin[nkin0 + b]);
+    for (int b = 0; b < nkin2; ++b) k2.add(kin[nkin0 + nkin1 + b]);
+    for (int b = 0; b < nfield; ++b) { f0.add(field[3 * b]); f1.add(field[3 * b + 1]); f2.add(field[3 * b + 2]); }
+    for (int s = 0; s < nshell; ++s) { ei.add(spec[s]); ec.add(spec[nshell + s]); eq.add(spec[2 * nshell + s]); }
+    const double kin_grad = k0.val() * kin_w0 + k1.val() * kin_w1 + k2.val() * kin_w2;
+    const double e_int = alpha * beta * f1.val() / ntot;
+    out[0] = f0.val() / ntot;                         // mass
+    out[1] = 2.0 * alpha * alpha * kin_grad + e_int;  // energy
+    out[2] = 0.5 * f2.val() / ntot;                   // e_kin
+    out[3] = ei.val();
+    out[4] = ec.val();
+    out[5] = eq.val();
+    out[6] = e_int;
+  }
+}
+
+// ----------------------------------------------------------------- loss and its gradient
+// f0 <- w_x + i w_y, f1 <- w_z (d0, d1, d2 keep the derivatives)
+template <class Real>
+__global__ __launch_bounds__(256) void k_loss_fields(const void* psi, const void* d0, const void* d1, const void* d2,
+                                                     void* f0, void* f1, long n, double alpha) {
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+    const cplx<Real> p = ldc<Real>(psi, i);
+    const cplx<Real> dx = ldc<Real>(d0, i), dy = ldc<Real>(d1, i), dz = ldc<Real>(d2, i);
+    const double pr = p.x, pi = p.y, amp = sqrt(pr * pr + pi * pi);
+    double wx = 0, wy = 0, wz = 0;
+    if (amp > 0.0) {
+      const double f = 2.0 * alpha / amp;
+      wx = f * (pr * (double)dx.y - pi * (double)dx.x);
+      wy = f * (pr * (double)dy.y - pi * (double)dy.x);
+      wz = f * (pr * (double)dz.y - pi * (double)dz.x);
+    }
+    stc<Real>(f0, i, wx, wy);
+    stc<Real>(f1, i, wz, 0.0);
+  }
+}
+
+// For each pair {k, -k}: unpack w, project onto the incompressible part, keep
+// shells smin..smax, add 1/2|g|^2 to J, and write back g/Ntot packed as
+// F0 = g_x + i g_y, F1 = g_z (so the inverse transforms give N^-3 IFFT(g)).
+template <class Real>
+__global__ __launch_bounds__(256) void k_loss_spectral(void* F0, void* F1, int nx, int ny, int nz, int smin, int smax,
+                                                       double* __restrict__ partial) {
+  __shared__ double sh[4];
+  const long n = (long)nx * ny * nz;
+  const double inv = 1.0 / (double)n;
+  Neu acc;
+  cplx<Real>* P0 = reinterpret_cast<cplx<Real>*>(F0);
+  cplx<Real>* P1 = reinterpret_cast<cplx<Real>*>(F1);
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+    const int ix = (int)(i % nx), iy = (int)((i / nx) % ny), iz = (int)(i / ((long)nx * ny));
+    const long m = (long)((nz - iz) % nz) * nx * ny + (long)((ny - iy) % ny) * nx + (nx - ix) % nx;
+    if (m < i) continue;                       // the pair is handled at its smaller index
+    const cplx<Real> z0 = P0[i], z0m = P0[m], z1 = P1[i], z1m = P1[m];
+    const int kx = kfreq(ix, nx), ky = kfreq(iy, ny), kz = kfreq(iz, nz);
+    const long k2 = (long)kx * kx + (long)ky * ky + (long)kz * kz;
+    const int s = shell_of(k2);
+    const bool in = (s >= smin && s <= smax);
+    // w at k (normalised)
+    const double wxr = 0.5 * ((double)z0.x + z0m.x) * inv, wxi = 0.5 * ((double)z0.y - z0m.y) * inv;
+    const double wyr = 0.5 * ((double)z0.y + z0m.y) * inv, wyi = -0.5 * ((double)z0.x - z0m.x) * inv;
+    const double wzr = 0.5 * ((double)z1.x + z1m.x) * inv, wzi = 0.5 * ((double)z1.y - z1m.y) * inv;
+    double gxr = 0, gxi = 0, gyr = 0, gyi = 0, gzr = 0, gzi = 0;
+    if (in) {
+      double cr = 0, ci = 0;
+      if (k2 > 0) {
+        cr = (kx * wxr + ky * wyr + kz * wzr) / (double)k2;
+        ci = (kx * wxi + ky * wyi + kz * wzi) / (double)k2;
+      }
+      gxr = wxr - kx * cr; gxi = wxi - kx * ci;
+      gyr = wyr - ky * cr; gyi = wyi - ky * ci;
+      gzr = wzr - kz * cr; gzi = wzi - kz * ci;
+      const double e = 0.5 * (gxr * gxr + gxi * gxi + gyr * gyr + gyi * gyi + gzr * gzr + gzi * gzi);
+      acc.add(m == i ? e : 2.0 * e);
+    }
+    // g(-k) = conj(g(k)) (real fields); pack: G0 = gx + i gy, G1 = gz
+    P0[i] = mk(Real((gxr - gyi) * inv), Real((gxi + gyr) * inv));
+    P1[i] = mk(Real(gzr * inv), Real(gzi * inv));
+    if (m != i) {
+      P0[m] = mk(Real((gxr + gyi) * inv), Real((-gxi + gyr) * inv));
+      P1[m] = mk(Real(gzr * inv), Real(-gzi * inv));
+    }
+  }
+  const double tot = block_sum256(acc.val(), sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+// lam = sum_j [ -i h_j d_j - G_j w_j psi/|psi|^2 ],  h_j = 2 alpha G_j/|psi|;
+// then d_j <- h_j psi (to be differentiated along j).  G0 = Gx + i Gy, G1 = Gz.
+template <class Real>
+__global__ __launch_bounds__(256) void k_loss_lambda1(const void* psi, void* d0, void* d1, void* d2, const void* G0,
+                                                      const void* G1, void* lam, long n, double alpha) {
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+    const cplx<Real> p = ldc<Real>(psi, i);
+    const double pr = p.x, pi = p.y, rho = pr * pr + pi * pi, amp = sqrt(rho);
+    double lr = 0, li = 0;
+    double hx = 0, hy = 0, hz = 0;
+    if (amp > 0.0) {
+      const cplx<Real> g0 = ldc<Real>(G0, i), g1 = ldc<Real>(G1, i);
+      const double G[3] = {(double)g0.x, (double)g0.y, (double)g1.x};
+      const void* dp[3] = {d0, d1, d2};
+      double h[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const cplx<Real> d = ldc<Real>(dp[j], i);
+        const double dr = d.x, di = d.y;
+        const double w = 2.0 * alpha * (pr * di - pi * dr) / amp;
+        h[j] = 2.0 * alpha * G[j] / amp;
+        // -i h d = h * (di, -dr)
+        lr += h[j] * di; li -= h[j] * dr;
+        const double f = G[j] * w / rho;
+        lr -= f * pr; li -= f * pi;
+      }
+      hx = h[0]; hy = h[1]; hz = h[2];
+    }
+    stc<Real>(lam, i, lr, li);
+    stc<Real>(d0, i, hx * pr, hx * pi);
+    stc<Real>(d1, i, hy * pr, hy * pi);
+    stc<Real>(d2, i, hz * pr, hz * pi);
+  }
+}
+
+// lam += -i (e0 + e1 + e2), e_j = d/dj (h_j psi)
+template <class Real>
+__global__ __launch_bounds__(256) void k_loss_lambda2(void* lam, const void* e0, const void* e1, const void* e2, long n) {
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+    const cplx<Real> l = ldc<Real>(lam, i);
+    const cplx<Real> a = ldc<Real>(e0, i), b = ldc<Real>(e1, i), c = ldc<Real>(e2, i);
+    const double sr = (double)a.x + b.x + c.x, si = (double)a.y + b.y + c.y;
+    stc<Real>(lam, i, (double)l.x + si, (double)l.y - sr);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ p, int n, double* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    Neu a;
+    for (int i = 0; i < n; ++i) a.add(p[i]);
+    out[0] = a.val();
+  }
+}
+
+template <class Real>
+__global__ void k_phase_grad(const void* psi0, const void* lam0, double* out, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const cplx<Real> p = ldc<Real>(psi0, i), l = ldc<Real>(lam0, i);
+    out[i] = (double)l.y * p.x - (double)l.x * p.y;      // Im(lam conj(psi))
+  }
+}
+
+// ----------------------------------------------------------------- structure function
+// Per-axis power sums P_j(k) = sum over pencils |F_j(rho - 1)|^2 (natural order along
+// axis j).  F holds the axis-j transform; axis j index of element i is (i / div) % nj.
+__global__ __launch_bounds__(64) void k_axis_power_c128(const void* F, long n, long div, int nj, long chunk,
+                                                        double* __restrict__ part);
+__global__ __launch_bounds__(64) void k_axis_power_c64(const void* F, long n, long div, int nj, long chunk,
+                                                       double* __restrict__ part);
+
+template <class Real>
+__device__ __forceinline__ void axis_power(const void* F, long n, long div, int nj, long chunk, double* part) {
+  extern __shared__ double bins[];
+  for (int i = threadIdx.x; i < nj; i += 64) bins[i] = 0.0;
+  __syncthreads();
+  const long i0 = (long)blockIdx.x * chunk;
+  const long i1 = (i0 + chunk < n) ? i0 + chunk : n;
+  for (long i = i0 + threadIdx.x; i < i1; i += 64) {
+    const cplx<Real> z = ldc<Real>(F, i);
+    atomicAdd(&bins[(i / div) % nj], (double)z.x * z.x + (double)z.y * z.y);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nj; i += 64) part[(long)blockIdx.x * nj + i] = bins[i];
+}
+__global__ __launch_bounds__(64) void k_axis_power_c128(const void* F, long n, long div, int nj, long chunk, double* part) {
+  axis_power<double>(F, n, div, nj, chunk, part);
+}
+__global__ __launch_bounds__(64) void k_axis_power_c64(const void* F, long n, long div, int nj, long chunk, double* part) {
+  axis_power<float>(F, n, div, nj, chunk, part);
+}
+
+// S(m) = (1/3) sum_j 2/(Ntot N_j) sum_k P_j(k) (1 - cos(2 pi k m / N_j)), m = 1..N/2
+__global__ __launch_bounds__(256) void k_structure_final(const double* __restrict__ part, int nblk, int nj, double ntot,
+                                                         double* __restrict__ out) {
+  extern __shared__ double pk[];              // [3][nj]: fixed-order sums of the per-block partials
+  for (int q = threadIdx.x; q < 3 * nj; q += 256) {
+    const int ax = q / nj, k = q % nj;
+    Neu a;
+    for (int b = 0; b < nblk; ++b) a.add(part[((long)ax * nblk + b) * nj + k]);
+    pk[q] = a.val();
+  }
+  __syncthreads();
+  for (int m = 1 + threadIdx.x; m <= nj / 2; m += 256) {
+    Neu a;
+    for (int ax = 0; ax < 3; ++ax)
+      for (int k = 0; k < nj; ++k) {
+        const long km = ((long)k * m) % nj;
+        a.add(pk[ax * nj + k] * (1.0 - cospi(2.0 * (double)km / (double)nj)));
+      }
+    out[m - 1] = a.val() * 2.0 / (3.0 * ntot * (double)nj);
+  }
+}
+
+// ----------------------------------------------------------------- launch wrappers
+static unsigned grid_for(long n, int threads, unsigned cap = 4096) {
+  long g = (n + threads - 1) / threads;
+  if (g < 1) g = 1;
+  return (unsigned)(g > cap ? cap : g);
+}
+
+void launch_init_phase(int prec, const double* theta, void* psi, long n, hipStream_t st) {
+  if (prec == P_C128) hipLaunchKernelGGL(k_init_phase<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, theta, psi, n);
+  else hipLaunchKernelGGL(k_init_phase<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, theta, psi, n);
+}
+void launch_nonlinear(int prec, void* psi, long n, double coef, hipStream_t st) {
+  if (prec == P_C128) hipLaunchKernelGGL(k_nonlinear<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, psi, n, coef);
+  else hipLaunchKernelGGL(k_nonlinear<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, psi, n, coef);
+}
+void launch_scale_copy(int prec, const void* in, void* out, long n, double scale, hipStream_t st) {
+  if (prec == P_C128) hipLaunchKernelGGL(k_scale_copy<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, in, out, n, scale);
+  else hipLaunchKernelGGL(k_scale_copy<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, in, out, n, scale);
+}
+void launch_mult3(int prec, void* f, int nx, int ny, int nz, const void* mx, const void* my, const void* mz, hipStream_t st) {
+  const long n = (long)nx * ny * nz;
+  if (prec == P_C128) hipLaunchKernelGGL(k_mult3<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, f, nx, ny, nz, mx, my, mz);
+  else hipLaunchKernelGGL(k_mult3<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, f, nx, ny, nz, mx, my, mz);
+}
+void launch_diag_fields(int prec, const void* psi, void* f0, void* f1, void* f2, long n, double alpha, double* partial,
+                        unsigned blocks, hipStream_t st) {
+  if (prec == P_C128) hipLaunchKernelGGL(k_diag_fields<double>, dim3(blocks), dim3(256), 0, st, psi, f0, f1, f2, n, alpha, partial);
+  else hipLaunchKernelGGL(k_diag_fields<float>, dim3(blocks), dim3(256), 0, st, psi, f0, f1, f2, n, alpha, partial);
+}
+void launch_spectral(int prec, const void* F0, const void* F1, const void* F2, int nx, int ny, int nz, double alpha,
+                     double beta, int nshell, unsigned blocks, long chunk, double* bins, hipStream_t st) {
+  const size_t sh = sizeof(double) * 4 * (size_t)nshell;
+  if (prec == P_C128)
+    hipLaunchKernelGGL(k_spectral<double>, dim3(blocks), dim3(64), sh, st, F0, F1, F2, nx, ny, nz, alpha, beta, nshell, chunk, bins);
+  else
+    hipLaunchKernelGGL(k_spectral<float>, dim3(blocks), dim3(64), sh, st, F0, F1, F2, nx, ny, nz, alpha, beta, nshell, chunk, bins);
+}
+void launch_finalize_diag(const double* kin, int nk0, int nk1, int nk2, double w0, double w1, double w2,
+                          const double* field, int nfield, const double* bins, int nbins, int nshell, double alpha,
+                          double beta, double ntot, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize_diag, dim3(1), dim3(256), sizeof(double) * 4 * (size_t)nshell, st, kin, nk0, nk1, nk2, w0, w1, w2, field, nfield, bins,
+                     nbins, nshell, alpha, beta, ntot, out);
+}
+void launch_loss_fields(int prec, const void* psi, const void* d0, const void* d1, const void* d2, void* f0, void* f1,
+                        long n, double alpha, hipStream_t st) {
+  if (prec == P_C128) hipLaunchKernelGGL(k_loss_fields<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, psi, d0, d1, d2, f0, f1, n, alpha);
+  else hipLaunchKernelGGL(k_loss_fields<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, psi, d0, d1, d2, f0, f1, n, alpha);
+}
+void launch_loss_spectral(int prec, void* F0, void* F1, int nx, int ny, int nz, int smin, int smax, double* partial,
+                          unsigned blocks, hipStream_t st) {
+  if (prec == P_C128) hipLaunchKernelGGL(k_loss_spectral<double>, dim3(blocks), dim3(256), 0, st, F0, F1, nx, ny, nz, smin, smax, partial);
+  else hipLaunchKernelGGL(k_loss_spectral<float>, dim3(blocks), dim3(256), 0, st, F0, F1, nx, ny, nz, smin, smax, partial);
+}
+void launch_loss_lambda1(int prec, const void* psi, void* d0, void* d1, void* d2, const void* G0, const void* G1,
+                         void* lam, long n, double alpha, hipStream_t st) {
+  if (prec == P_C128) hipLaunchKernelGGL(k_loss_lambda1<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, psi, d0, d1, d2, G0, G1, lam, n, alpha);
+  else hipLaunchKernelGGL(k_loss_lambda1<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, psi, d0, d1, d2, G0, G1, lam, n, alpha);
+}
+void launch_loss_lambda2(int prec, void* lam, const void* e0, const void* e1, const void* e2, long n, hipStream_t st) {
+  if (prec == P_C128) hipLaunchKernelGGL(k_loss_lambda2<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, lam, e0, e1, e2, n);
+  else hipLaunchKernelGGL(k_loss_lambda2<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, lam, e0, e1, e2, n);
+}
+void launch_sum_partials(const double* p, int n, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, st, p, n, out);
+}
+void launch_phase_grad(int prec, const void* psi0, const void* lam0, double* out, long n, hipStream_t st) {
+  if (prec == P_C128) hipLaunchKernelGGL(k_phase_grad<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, psi0, lam0, out, n);
+  else hipLaunchKernelGGL(k_phase_grad<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, psi0, lam0, out, n);
+}
+void launch_axis_power(int prec, const void* F, long n, long div, int nj, unsigned blocks, long chunk, double* part,
+                       hipStream_t st) {
+  const size_t sh = sizeof(double) * (size_t)nj;
+  if (prec == P_C128) hipLaunchKernelGGL(k_axis_power_c128, dim3(blocks), dim3(64), sh, st, F, n, div, nj, chunk, part);
+  else hipLaunchKernelGGL(k_axis_power_c64, dim3(blocks), dim3(64), sh, st, F, n, div, nj, chunk, part);
+}
+void launch_structure_final(const double* part, int nblk, int nj, double ntot, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_structure_final, dim3(1), dim3(256), sizeof(double) * 3 * (size_t)nj, st, part, nblk, nj, ntot, out);
+}
+
+}  // namespace gpk

@@ -1,0 +1,56 @@
+// Registry of compiled axis-pass schedules (one entry per grid length, precision
+// and variant).  Each instantiation unit registers its launchers at load time.
+#pragma once
+
+#include <vector>
+
+#include "gp_pass.h"
+
+namespace gpk {
+
+enum Prec { P_C128 = 0, P_C64 = 1 };
+
+struct PassEntry {
+  int n, prec, variant;
+  int T, W, NS, threads;
+  int radix[3];
+  PassLauncher fn[2][V_COUNT];   // [KIND][Variant]
+};
+
+std::vector<PassEntry>& registry();
+
+struct Registrar {
+  explicit Registrar(const PassEntry& e) { registry().push_back(e); }
+};
+
+template <class Real, class S, int KIND>
+void fill(PassEntry& e) {
+  e.fn[KIND][V_PROP] = &launch_pass<Real, S, KIND, PROP, PRO_NONE>;
+  e.fn[KIND][V_PROP_NL] = &launch_pass<Real, S, KIND, PROP, PRO_NL>;
+  e.fn[KIND][V_PROP_ADJ] = &launch_pass<Real, S, KIND, PROP, PRO_ADJ_NL>;
+  e.fn[KIND][V_PROP_KIN] = &launch_pass<Real, S, KIND, PROP, PRO_KIN>;
+  e.fn[KIND][V_FWD] = &launch_pass<Real, S, KIND, FWD, PRO_NONE>;
+  e.fn[KIND][V_FWD_DENSITY] = &launch_pass<Real, S, KIND, FWD, PRO_DENSITY>;
+  e.fn[KIND][V_INV] = &launch_pass<Real, S, KIND, INV, PRO_NONE>;
+}
+
+template <class Real, class S>
+PassEntry make_entry(int prec, int variant) {
+  static_assert(S::THREADS % 64 == 0, "workgroup must be whole wavefronts");
+  PassEntry e{};
+  e.n = S::N; e.prec = prec; e.variant = variant;
+  e.T = S::T; e.W = S::W; e.NS = S::NS; e.threads = S::THREADS;
+  for (int s = 0; s < 3; ++s) e.radix[s] = s < S::NS ? S::rad(s) : 1;
+  fill<Real, S, CONTIG>(e);
+  fill<Real, S, STRIDED>(e);
+  return e;
+}
+
+}  // namespace gpk
+
+#define GPK_CAT2(a, b) a##b
+#define GPK_CAT(a, b) GPK_CAT2(a, b)
+// GPK_SCHED(real, prec, variant, N, T, W, R0, R1, R2)
+#define GPK_SCHED(REAL, PREC, VAR, N, T, W, R0, R1, R2)                                         \
+  static ::gpk::Registrar GPK_CAT(gpk_reg_, __LINE__)(                                          \
+      ::gpk::make_entry<REAL, ::gpk::Sched<N, T, W, R0, R1, R2>>(PREC, VAR));

@@ -1,0 +1,940 @@
+// Host runtime of the Gross-Pitaevskii library: plans, FP64 table generation,
+// pass sequencing of the split step, diagnostics and adjoint pipelines, the
+// ensemble (batch) path with HIP graph capture, and the C ABI of include/gp.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/gp.h"
+#include "gp_point.h"
+
+namespace gpk {
+
+std::vector<PassEntry>& registry() {
+  static std::vector<PassEntry> r;
+  return r;
+}
+
+namespace {
+
+thread_local std::string g_err;
+
+gp_status fail(gp_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+// ----------------------------------------------------------------- FP64 tables
+// cos and sin of 2 pi num/den with the angle reduced exactly in integers to
+// [0, pi/4] before calling the libm routines.
+void cis2pi(long num, long den, double* c, double* s) {
+  long m = ((num % den) + den) % den;
+  // 8 m = oct * den + r, angle = (pi/4)(oct + r/den)
+  const long oct = (8 * m) / den;
+  const long r = 8 * m - oct * den;
+  // reduce to the first octant
+  double a;
+  bool swap = false;
+  if (oct % 2 == 0) { a = (M_PI / 4) * double(r) / double(den); }
+  else { a = (M_PI / 4) * double(den - r) / double(den); swap = true; }
+  double cc = std::cos(a), ss = std::sin(a);
+  if (swap) std::swap(cc, ss);        // angle in octant 2q+1 measured from the next axis
+  const long q = oct / 2;              // quadrant
+  switch (q) {
+    case 0: *c = cc; *s = ss; break;
+    case 1: *c = -ss; *s = cc; break;
+    case 2: *c = -cc; *s = -ss; break;
+    default: *c = ss; *s = -cc; break;
+  }
+}
+
+int kfreq(int i, int n) { return (2 * i < n) ? i : i - n; }
+
+// natural frequency index -> position of the DIF output (digit reversal)
+int freq_pos(const PassEntry& e, int k) {
+  int p = 0, K = 1;
+  for (int s = 0; s < e.NS; ++s) {
+    int M = 1;
+    for (int i = s + 1; i < e.NS; ++i) M *= e.radix[i];
+    p += ((k / K) % e.radix[s]) * M;
+    K *= e.radix[s];
+  }
+  return p;
+}
+
+const int kSupported[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024};
+
+const PassEntry* find_entry(int n, int prec, int variant) {
+  for (const auto& e : registry())
+    if (e.n == n && e.prec == prec && e.variant == variant) return &e;
+  return nullptr;
+}
+
+enum Tau { TAU_H = 0, TAU_DT = 1, TAU_MH = 2, TAU_MDT = 3, NTAU = 4 };
+
+struct Axis {
+  int n = 1;
+  int kind = CONTIG;
+  const PassEntry* e = nullptr;
+  long npencils = 0, inner = 1, outer = 0, es = 1;
+  unsigned blocks = 0;
+  // device tables (working precision unless noted)
+  void* tw = nullptr;
+  void* mult[NTAU] = {};    // exp(-i alpha k^2 tau)/n, position order
+  void* deriv = nullptr;    // i k~/n, position order
+  double* ksq = nullptr;    // k^2, position order (double)
+  void* nat[NTAU] = {};     // exp(-i alpha k^2 tau)/n, natural order
+};
+
+}  // namespace
+}  // namespace gpk
+
+using namespace gpk;
+
+struct gp_plan_s {
+  gp_desc d{};
+  hipStream_t stream = nullptr;
+  int prec = P_C128;
+  size_t S = 16;
+  long ntot = 0;
+  int nshell = 0;
+  Axis ax[3];
+  std::vector<void*> allocs;       // device allocations owned by the plan
+  std::map<std::pair<int, double>, void*> substep_tables;   // gp_substep_linear cache
+  // reduction partials
+  double* kin_part = nullptr;      // blocks(x) + blocks(y) + blocks(z)
+  double* field_part = nullptr;    // 3 * field_blocks
+  unsigned field_blocks = 0;
+  double* bins_part = nullptr;     // spec_blocks * 4 * nshell
+  unsigned spec_blocks = 0;
+  long spec_chunk = 0;
+  double* power_part = nullptr;    // 3 * pow_blocks * nx
+  unsigned pow_blocks = 0;
+  long pow_chunk = 0;
+  double* loss_part = nullptr;     // field_blocks
+  double* d_result = nullptr;      // 8 + 4 * nshell
+  double* h_result = nullptr;      // pinned mirror
+  bool broken = false;
+  bool own_stream = false;         // stream created by the plan (batch plans on the null stream)
+  std::string sched_name[3];
+  // ensemble
+  bool is_batch = false;
+  std::vector<gp_plan_s*> runs;
+  struct Group { int n; std::vector<int> members; RunPtrs* d_ptrs = nullptr; size_t nptrs = 0; };
+  std::vector<Group> groups;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<void*> graph_key;
+  int64_t graph_steps = 0;
+};
+
+namespace gpk {
+namespace {
+
+#define HIPCHK(plan, expr)                                                                   \
+  do {                                                                                       \
+    hipError_t _e = (expr);                                                                  \
+    if (_e != hipSuccess) {                                                                  \
+      if (plan) (plan)->broken = true;                                                       \
+      return fail(GP_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(_e));                \
+    }                                                                                        \
+  } while (0)
+
+gp_status check_launch(gp_plan_s* p) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    p->broken = true;
+    return fail(GP_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+  }
+  return GP_OK;
+}
+
+gp_status dev_alloc(gp_plan_s* p, void** ptr, size_t bytes) {
+  *ptr = nullptr;
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(ptr, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *ptr = nullptr;
+    return fail(GP_ERR_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  }
+  p->allocs.push_back(*ptr);
+  return GP_OK;
+}
+
+// upload complex FP64 values in working precision
+gp_status upload_cplx(gp_plan_s* p, void** dst, const std::vector<double>& reim) {
+  const size_t n = reim.size() / 2;
+  gp_status st = dev_alloc(p, dst, n * p->S);
+  if (st != GP_OK) return st;
+  if (p->prec == P_C128) {
+    HIPCHK(p, hipMemcpy(*dst, reim.data(), n * 16, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> f(reim.size());
+    for (size_t i = 0; i < reim.size(); ++i) f[i] = (float)reim[i];
+    HIPCHK(p, hipMemcpy(*dst, f.data(), n * 8, hipMemcpyHostToDevice));
+  }
+  return GP_OK;
+}
+
+gp_status upload_f64(gp_plan_s* p, double** dst, const std::vector<double>& v) {
+  gp_status st = dev_alloc(p, (void**)dst, v.size() * sizeof(double));
+  if (st != GP_OK) return st;
+  HIPCHK(p, hipMemcpy(*dst, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
+  return GP_OK;
+}
+
+bool supported_n(int n) {
+  for (int s : kSupported) if (s == n) return true;
+  return false;
+}
+
+gp_status setup_axis(gp_plan_s* p, int a, int variant) {
+  Axis& A = p->ax[a];
+  const int n = A.n;
+  const int nx = p->d.n[0], ny = p->d.n[1], nz = p->d.n[2];
+  if (a == 0) { A.kind = CONTIG; A.npencils = (long)ny * nz; A.inner = 1; A.outer = nx; A.es = 1; }
+  else if (a == 1) { A.kind = STRIDED; A.npencils = (long)nx * nz; A.inner = nx; A.outer = (long)nx * ny; A.es = nx; }
+  else { A.kind = STRIDED; A.npencils = (long)nx * ny; A.inner = (long)nx * ny; A.outer = 0; A.es = (long)nx * ny; }
+  if (n == 1) { A.e = nullptr; A.blocks = 0; p->sched_name[a] = "N=1 (identity)"; return GP_OK; }
+  A.e = find_entry(n, p->prec, variant);
+  if (!A.e) return fail(GP_ERR_UNSUPPORTED, "no compiled schedule for axis length %d (variant %d)", n, variant);
+  A.blocks = (unsigned)((A.npencils + A.e->W - 1) / A.e->W);
+  char nm[128];
+  snprintf(nm, sizeof nm, "N=%d T=%d W=%d R=%dx%dx%d v%d", n, A.e->T, A.e->W, A.e->radix[0], A.e->radix[1],
+           A.e->radix[2], variant);
+  p->sched_name[a] = nm;
+  return GP_OK;
+}
+
+// tables of one axis (FP64 on the host, rounded to working precision)
+gp_status build_tables(gp_plan_s* p, int a) {
+  Axis& A = p->ax[a];
+  const int n = A.n;
+  const double alpha = p->d.alpha, dt = p->d.dt;
+  const double taus[NTAU] = {0.5 * dt, dt, -0.5 * dt, -dt};
+  std::vector<int> pos(n);
+  for (int k = 0; k < n; ++k) pos[k] = A.e ? freq_pos(*A.e, k) : k;
+  gp_status st;
+  if (A.e) {
+    std::vector<double> tw(2 * n);
+    for (int m = 0; m < n; ++m) cis2pi(-m, n, &tw[2 * m], &tw[2 * m + 1]);   // exp(-2 pi i m/n)
+    if ((st = upload_cplx(p, &A.tw, tw)) != GP_OK) return st;
+  }
+  for (int t = 0; t < NTAU; ++t) {
+    std::vector<double> mp(2 * n), mn(2 * n);
+    for (int k = 0; k < n; ++k) {
+      const double kk = (double)kfreq(k, n);
+      const double ph = alpha * kk * kk * taus[t];
+      const double c = std::cos(ph) / n, s = -std::sin(ph) / n;
+      mp[2 * pos[k]] = c; mp[2 * pos[k] + 1] = s;
+      mn[2 * k] = c; mn[2 * k + 1] = s;
+    }
+    if ((st = upload_cplx(p, &A.mult[t], mp)) != GP_OK) return st;
+    if ((st = upload_cplx(p, &A.nat[t], mn)) != GP_OK) return st;
+  }
+  std::vector<double> dv(2 * n), kq(n);
+  for (int k = 0; k < n; ++k) {
+    const int kf = kfreq(k, n);
+    const int k1 = (n % 2 == 0 && 2 * k == n) ? 0 : kf;
+    dv[2 * pos[k]] = 0.0; dv[2 * pos[k] + 1] = (double)k1 / n;       // i k~ / n
+    kq[pos[k]] = (double)kf * kf;
+  }
+  if ((st = upload_cplx(p, &A.deriv, dv)) != GP_OK) return st;
+  if ((st = upload_f64(p, &A.ksq, kq)) != GP_OK) return st;
+  return GP_OK;
+}
+
+int shell_of_host(long k2) {
+  const long q = 4 * k2;
+  long r = (long)std::sqrt((double)q);
+  while (r * r > q) --r;
+  while ((r + 1) * (r + 1) <= q) ++r;
+  return (int)((r + 1) / 2);
+}
+
+gp_status plan_init(gp_plan_s* p, const gp_desc* d, hipStream_t stream) {
+  p->d = *d;
+  p->stream = stream;
+  p->prec = d->prec;
+  p->S = d->prec == GP_C128 ? 16 : 8;
+  for (int a = 0; a < 3; ++a) p->ax[a].n = d->n[a];
+  p->ntot = (long)d->n[0] * d->n[1] * d->n[2];
+  const long kmax2 = (long)(d->n[0] / 2) * (d->n[0] / 2) + (long)(d->n[1] / 2) * (d->n[1] / 2) +
+                     (long)(d->n[2] / 2) * (d->n[2] / 2);
+  p->nshell = shell_of_host(kmax2) + 1;
+  gp_status st;
+  for (int a = 0; a < 3; ++a) {
+    if ((st = setup_axis(p, a, 0)) != GP_OK) return st;
+    if ((st = build_tables(p, a)) != GP_OK) return st;
+  }
+  // reduction partials
+  const long kin_n = (long)p->ax[0].blocks + p->ax[1].blocks + p->ax[2].blocks;
+  if ((st = dev_alloc(p, (void**)&p->kin_part, std::max(1L, kin_n) * sizeof(double))) != GP_OK) return st;
+  p->field_blocks = (unsigned)std::min<long>(1024, std::max<long>(1, (p->ntot + 4095) / 4096));
+  if ((st = dev_alloc(p, (void**)&p->field_part, 3 * p->field_blocks * sizeof(double))) != GP_OK) return st;
+  if ((st = dev_alloc(p, (void**)&p->loss_part, p->field_blocks * sizeof(double))) != GP_OK) return st;
+  p->spec_blocks = (unsigned)std::min<long>(2048, std::max<long>(1, (p->ntot + 4095) / 4096));
+  p->spec_chunk = (p->ntot + p->spec_blocks - 1) / p->spec_blocks;
+  if ((st = dev_alloc(p, (void**)&p->bins_part, (size_t)p->spec_blocks * 4 * p->nshell * sizeof(double))) != GP_OK)
+    return st;
+  p->pow_blocks = p->spec_blocks;
+  p->pow_chunk = p->spec_chunk;
+  const int nmax = std::max(d->n[0], std::max(d->n[1], d->n[2]));
+  if ((st = dev_alloc(p, (void**)&p->power_part, 3 * (size_t)p->pow_blocks * nmax * sizeof(double))) != GP_OK)
+    return st;
+  if ((st = dev_alloc(p, (void**)&p->d_result, (8 + 4 * (size_t)p->nshell + nmax) * sizeof(double))) != GP_OK)
+    return st;
+  hipError_t e = hipHostMalloc((void**)&p->h_result, (8 + 4 * (size_t)p->nshell + nmax) * sizeof(double),
+                               hipHostMallocDefault);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(GP_ERR_NOMEM, "hipHostMalloc failed: %s", hipGetErrorString(e));
+  }
+  return GP_OK;
+}
+
+void plan_free(gp_plan_s* p) {
+  if (!p) return;
+  for (auto* r : p->runs) plan_free(r);
+  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  for (void* a : p->allocs) (void)hipFree(a);
+  for (auto& g : p->groups) if (g.d_ptrs) (void)hipFree(g.d_ptrs);
+  if (p->h_result) (void)hipHostFree(p->h_result);
+  if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
+  delete p;
+}
+
+gp_status validate_desc(const gp_desc* d) {
+  if (!d) return fail(GP_ERR_ARG, "null descriptor");
+  for (int a = 0; a < 3; ++a) {
+    if (d->n[a] < 1) return fail(GP_ERR_ARG, "n[%d] = %d must be >= 1", a, d->n[a]);
+    if (!supported_n(d->n[a])) return fail(GP_ERR_UNSUPPORTED, "axis length n[%d] = %d is not supported", a, d->n[a]);
+  }
+  if (d->prec != GP_C128 && d->prec != GP_C64) return fail(GP_ERR_UNSUPPORTED, "precision %d", d->prec);
+  if (!std::isfinite(d->alpha) || !std::isfinite(d->beta) || !std::isfinite(d->dt))
+    return fail(GP_ERR_ARG, "alpha, beta and dt must be finite");
+  if (d->flags != 0) return fail(GP_ERR_ARG, "flags must be 0");
+  return GP_OK;
+}
+
+gp_status usable(const gp_plan_s* p) {
+  if (!p) return fail(GP_ERR_ARG, "null plan");
+  if (p->broken) return fail(GP_ERR_STATE, "plan is unusable after an earlier HIP error");
+  return GP_OK;
+}
+
+// ----------------------------------------------------------------- pass launch
+gp_status pass(gp_plan_s* p, int a, int var, const void* in, void* out, const void* mult, double nl_coef = 0.0,
+               const void* aux = nullptr, double scale = 1.0, double* kin = nullptr, const void* pmx = nullptr,
+               const void* pmy = nullptr) {
+  Axis& A = p->ax[a];
+  if (A.n == 1) {
+    // one point along the axis: the transform is the identity and k = 0, so the
+    // propagator tables are 1 (derivatives are handled by the callers)
+    if (var == V_PROP_NL || var == V_PROP_ADJ || var == V_FWD_DENSITY)
+      return fail(GP_ERR_STATE, "internal: fused prologue on an axis of length 1");
+    if (in != out || scale != 1.0) launch_scale_copy(p->prec, in, out, p->ntot, scale, p->stream);
+    return check_launch(p);
+  }
+  PassArgs g{};
+  g.batch = nullptr;
+  g.in = in; g.out = out; g.mult = mult; g.tw = A.tw; g.aux = aux; g.pmx = pmx; g.pmy = pmy;
+  g.ksq = A.ksq; g.kin_partial = kin; g.nl_coef = nl_coef; g.scale = scale;
+  g.npencils = A.npencils; g.inner = A.inner; g.outer = A.outer; g.es = A.es; g.nx = p->d.n[0];
+  A.e->fn[A.kind][var](g, A.blocks, 1, p->stream);
+  return check_launch(p);
+}
+
+int first_real_axis(const gp_plan_s* p) {
+  for (int a = 0; a < 3; ++a) if (p->ax[a].n > 1) return a;
+  return -1;
+}
+
+// L(tau) on psi in place, the nonlinear rotation of coefficient nl (if any) fused in front
+gp_status linear_all(gp_plan_s* p, void* psi, int tau, bool with_nl, double nl) {
+  const int c = first_real_axis(p);
+  gp_status st;
+  if (c < 0) {   // 1x1x1 grid: only the nonlinear rotation acts (k = 0)
+    if (with_nl) { launch_nonlinear(p->prec, psi, p->ntot, nl, p->stream); return check_launch(p); }
+    return GP_OK;
+  }
+  for (int a = 0; a < 3; ++a) {
+    if (p->ax[a].n == 1) continue;
+    const bool nl_here = with_nl && a == c;
+    if ((st = pass(p, a, nl_here ? V_PROP_NL : V_PROP, psi, psi, p->ax[a].mult[tau], nl)) != GP_OK) return st;
+  }
+  return GP_OK;
+}
+
+gp_status step_n(gp_plan_s* p, void* psi, int64_t nsteps) {
+  if (nsteps == 0) return GP_OK;
+  const bool back = nsteps < 0;
+  const int64_t n = back ? -nsteps : nsteps;
+  const int th = back ? TAU_MH : TAU_H, tf = back ? TAU_MDT : TAU_DT;
+  const double nl = p->d.beta * (back ? -p->d.dt : p->d.dt);
+  gp_status st;
+  if ((st = linear_all(p, psi, th, false, 0.0)) != GP_OK) return st;
+  for (int64_t s = 0; s < n; ++s)
+    if ((st = linear_all(p, psi, s + 1 < n ? tf : th, true, nl)) != GP_OK) return st;
+  return GP_OK;
+}
+
+gp_status fft3(gp_plan_s* p, const void* in, void* out, int dir) {
+  gp_status st;
+  const void* src = in;
+  for (int a = 0; a < 3; ++a) {
+    const double sc = dir < 0 ? 1.0 / p->ax[a].n : 1.0;
+    if ((st = pass(p, a, dir < 0 ? V_FWD : V_INV, src, out, nullptr, 0.0, nullptr, sc)) != GP_OK) return st;
+    src = out;
+  }
+  return GP_OK;
+}
+
+// unnormalised forward 3-D transform in place
+gp_status fwd3_unnorm(gp_plan_s* p, void* f) {
+  gp_status st;
+  for (int a = 0; a < 3; ++a)
+    if ((st = pass(p, a, V_FWD, f, f, nullptr, 0.0, nullptr, 1.0)) != GP_OK) return st;
+  return GP_OK;
+}
+gp_status inv3_unnorm(gp_plan_s* p, void* f) {
+  gp_status st;
+  for (int a = 0; a < 3; ++a)
+    if ((st = pass(p, a, V_INV, f, f, nullptr, 0.0, nullptr, 1.0)) != GP_OK) return st;
+  return GP_OK;
+}
+
+void* field(const gp_plan_s* p, void* work, int i) { return (char*)work + (size_t)i * p->ntot * p->S; }
+
+// derivative passes psi -> F0..F2 with kinetic partials
+gp_status derivatives(gp_plan_s* p, const void* psi, void* work, bool kin) {
+  gp_status st;
+  double* kp = p->kin_part;
+  for (int a = 0; a < 3; ++a) {
+    void* out = field(p, work, a);
+    if (p->ax[a].n == 1) {
+      HIPCHK(p, hipMemsetAsync(out, 0, p->ntot * p->S, p->stream));
+      continue;
+    }
+    if ((st = pass(p, a, kin ? V_PROP_KIN : V_PROP, psi, out, p->ax[a].deriv, 0.0, nullptr, 1.0, kin ? kp : nullptr)) !=
+        GP_OK)
+      return st;
+    kp += p->ax[a].blocks;
+  }
+  return GP_OK;
+}
+
+gp_status diagnose(gp_plan_s* p, const void* psi, void* work) {
+  gp_status st;
+  if ((st = derivatives(p, psi, work, true)) != GP_OK) return st;
+  void* f0 = field(p, work, 0);
+  void* f1 = field(p, work, 1);
+  void* f2 = field(p, work, 2);
+  launch_diag_fields(p->prec, psi, f0, f1, f2, p->ntot, p->d.alpha, p->field_part, p->field_blocks, p->stream);
+  if ((st = check_launch(p)) != GP_OK) return st;
+  for (void* f : {f0, f1, f2})
+    if ((st = fwd3_unnorm(p, f)) != GP_OK) return st;
+  launch_spectral(p->prec, f0, f1, f2, p->d.n[0], p->d.n[1], p->d.n[2], p->d.alpha, p->d.beta, p->nshell,
+                  p->spec_blocks, p->spec_chunk, p->bins_part, p->stream);
+  if ((st = check_launch(p)) != GP_OK) return st;
+  const double nt = (double)p->ntot;
+  const int nk0 = p->ax[0].n > 1 ? (int)p->ax[0].blocks : 0;
+  const int nk1 = p->ax[1].n > 1 ? (int)p->ax[1].blocks : 0;
+  const int nk2 = p->ax[2].n > 1 ? (int)p->ax[2].blocks : 0;
+  launch_finalize_diag(p->kin_part, nk0, nk1, nk2, 1.0 / (nt * p->ax[0].n), 1.0 / (nt * p->ax[1].n),
+                       1.0 / (nt * p->ax[2].n), p->field_part, (int)p->field_blocks, p->bins_part,
+                       (int)p->spec_blocks, p->nshell, p->d.alpha, p->d.beta, nt, p->d_result, p->stream);
+  if ((st = check_launch(p)) != GP_OK) return st;
+  const size_t bytes = (7 + 4 * (size_t)p->nshell) * sizeof(double);
+  HIPCHK(p, hipMemcpyAsync(p->h_result, p->d_result, bytes, hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  return GP_OK;
+}
+
+gp_status copy_energies(gp_plan_s* p, gp_energy* out) {
+  const double* r = p->h_result;
+  gp_energy e{r[0], r[1], r[2], r[3], r[4], r[5], r[6]};
+  if (out) *out = e;
+  for (int i = 0; i < 7; ++i)
+    if (!std::isfinite(r[i])) return fail(GP_ERR_NONFINITE, "diagnostic %d is not finite", i);
+  return GP_OK;
+}
+
+}  // namespace
+}  // namespace gpk
+
+// =================================================================== C ABI
+extern "C" {
+
+gp_status gp_plan(const gp_desc* d, void* hip_stream, gp_plan_t** out) {
+  if (!out) return fail(GP_ERR_ARG, "null output pointer");
+  *out = nullptr;
+  gp_status st = validate_desc(d);
+  if (st != GP_OK) return st;
+  auto* p = new gp_plan_s();
+  st = plan_init(p, d, (hipStream_t)hip_stream);
+  if (st != GP_OK) {
+    std::string msg = g_err;
+    plan_free(p);
+    g_err = msg;
+    return st;
+  }
+  *out = p;
+  g_err.clear();
+  return GP_OK;
+}
+
+gp_status gp_plan_destroy(gp_plan_t* p) {
+  if (!p) return fail(GP_ERR_ARG, "null plan");
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  else (void)hipDeviceSynchronize();
+  plan_free(p);
+  return GP_OK;
+}
+
+size_t gp_state_bytes(const gp_plan_t* p, int32_t run) {
+  if (!p) return 0;
+  if (p->is_batch) {
+    if (run < 0 || run >= (int32_t)p->runs.size()) return 0;
+    return p->runs[run]->ntot * p->runs[run]->S;
+  }
+  return p->ntot * p->S;
+}
+
+size_t gp_work_bytes(const gp_plan_t* p) {
+  if (!p) return 0;
+  if (p->is_batch) {
+    size_t m = 0;
+    for (auto* r : p->runs) m = std::max(m, gp_work_bytes(r));
+    return m;
+  }
+  return 5 * p->ntot * p->S;
+}
+
+int32_t gp_nshell(const gp_plan_t* p) { return p ? p->nshell : 0; }
+
+const char* gp_last_error(void) { return g_err.c_str(); }
+
+const char* gp_schedule_name(const gp_plan_t* p, int32_t axis) {
+  if (!p || axis < 0 || axis > 2) return "";
+  return p->sched_name[axis].c_str();
+}
+
+int32_t gp_variant_count(int32_t n, int32_t prec) {
+  int c = 0;
+  for (const auto& e : registry()) if (e.n == n && e.prec == prec) ++c;
+  return c;
+}
+
+gp_status gp_select_variant(gp_plan_t* p, int32_t axis, int32_t variant) {
+  gp_status st = usable(p);
+  if (st != GP_OK) return st;
+  if (axis < 0 || axis > 2) return fail(GP_ERR_ARG, "axis %d", axis);
+  if (p->ax[axis].n == 1) return variant == 0 ? GP_OK : fail(GP_ERR_ARG, "axis of length 1 has one variant");
+  const PassEntry* e = find_entry(p->ax[axis].n, p->prec, variant);
+  if (!e) return fail(GP_ERR_ARG, "no variant %d for n = %d", variant, p->ax[axis].n);
+  // the radix order defines the position order of the tables: rebuild them
+  HIPCHK(p, p->stream ? hipStreamSynchronize(p->stream) : hipDeviceSynchronize());
+  const long old_blocks = p->ax[axis].blocks;
+  if ((st = setup_axis(p, axis, variant)) != GP_OK) return st;
+  if ((st = build_tables(p, axis)) != GP_OK) return st;
+  if ((long)p->ax[axis].blocks > old_blocks) {
+    const long kin_n = (long)p->ax[0].blocks + p->ax[1].blocks + p->ax[2].blocks;
+    if ((st = dev_alloc(p, (void**)&p->kin_part, kin_n * sizeof(double))) != GP_OK) return st;
+  }
+  return GP_OK;
+}
+
+gp_status gp_init_phase(gp_plan_t* p, const double* theta, void* psi) {
+  gp_status st = usable(p);
+  if (st != GP_OK) return st;
+  if (!theta || !psi) return fail(GP_ERR_ARG, "null theta or psi");
+  launch_init_phase(p->prec, theta, psi, p->ntot, p->stream);
+  return check_launch(p);
+}
+
+gp_status gp_substep_linear(gp_plan_t* p, void* psi, int32_t axis, double s) {
+  gp_status st = usable(p);
+  if (st != GP_OK) return st;
+  if (!psi) return fail(GP_ERR_ARG, "null psi");
+  if (axis < 0 || axis > 2) return fail(GP_ERR_ARG, "axis %d", axis);
+  if (!std::isfinite(s)) return fail(GP_ERR_ARG, "non-finite s");
+  Axis& A = p->ax[axis];
+  if (A.n == 1) return GP_OK;
+  if (p->substep_tables.size() > 256) return fail(GP_ERR_ARG, "too many distinct sub-step lengths on one plan");
+  // table for this s (one-off; the step loop uses the cached dt/2 and dt tables)
+  const int n = A.n;
+  std::vector<double> m(2 * n);
+  for (int k = 0; k < n; ++k) {
+    const double kk = (double)kfreq(k, n);
+    const double ph = p->d.alpha * kk * kk * s;
+    const int ps = freq_pos(*A.e, k);
+    m[2 * ps] = std::cos(ph) / n;
+    m[2 * ps + 1] = -std::sin(ph) / n;
+  }
+  void*& tab = p->substep_tables[{axis, s}];
+  if (!tab && (st = upload_cplx(p, &tab, m)) != GP_OK) return st;
+  return pass(p, axis, V_PROP, psi, psi, tab);
+}
+
+gp_status gp_substep_nonlinear(gp_plan_t* p, void* psi, double s) {
+  gp_status st = usable(p);
+  if (st != GP_OK) return st;
+  if (!psi) return fail(GP_ERR_ARG, "null psi");
+  if (!std::isfinite(s)) return fail(GP_ERR_ARG, "non-finite s");
+  launch_nonlinear(p->prec, psi, p->ntot, p->d.beta * s, p->stream);
+  return check_launch(p);
+}
+
+gp_status gp_step_n(gp_plan_t* p, void* psi, int64_t nsteps) {
+  gp_status st = usable(p);
+  if (st != GP_OK) return st;
+  if (p->is_batch) return fail(GP_ERR_STATE, "batch plan: use gp_step_n_batch");
+  if (!psi) return fail(GP_ERR_ARG, "null psi");
+  return step_n(p, psi, nsteps);
+}
+
+gp_status gp_step_literal_n(gp_plan_t* p, void* psi, int64_t nsteps) {
+  gp_status st = usable(p);
+  if (st != GP_OK) return st;
+  if (!psi) return fail(GP_ERR_ARG, "null psi");
+  const bool back = nsteps < 0;
+  const int64_t n = back ? -nsteps : nsteps;
+  const int th = back ? TAU_MH : TAU_H;
+  const double nl = p->d.beta * (back ? -p->d.dt : p->d.dt);
+  for (int64_t s = 0; s < n; ++s) {
+    for (int half = 0; half < 2; ++half) {
+      if ((st = fwd3_unnorm(p, psi)) != GP_OK) return st;
+      launch_mult3(p->prec, psi, p->d.n[0], p->d.n[1], p->d.n[2], p->ax[0].nat[th], p->ax[1].nat[th],
+                   p->ax[2].nat[th], p->stream);
+      if ((st = check_launch(p)) != GP_OK) return st;
+      if ((st = inv3_unnorm(p, psi)) != GP_OK) return st;
+      if (half == 0) {
+        launch_nonlinear(p->prec, psi, p->ntot, nl, p->stream);
+        if ((st = check_launch(p)) != GP_OK) return st;
+      }
+    }
+  }
+  return GP_OK;
+}
+
+gp_status gp_fft3(gp_plan_t* p, const void* in, void* out, int32_t dir) {
+  gp_status st = usable(p);
+  if (st != GP_OK) return st;
+  if (!in || !out) return fail(GP_ERR_ARG, "null field");
+  if (dir != -1 && dir != 1) return fail(GP_ERR_ARG, "dir must be -1 or +1");
+  return fft3(p, in, out, dir);
+}
+
+gp_status gp_energies(gp_plan_t* p, const void* psi, void* work, gp_energy* out) {
+  gp_status st = usable(p);
+  if (st != GP_OK) return st;
+  if (!psi || !work || !out) return fail(GP_ERR_ARG, "null argument");
+  if ((st = diagnose(p, psi, work)) != GP_OK) return st;
+  return copy_energies(p, out);
+}
+
+gp_status gp_spectra(gp_plan_t* p, const void* psi, void* work, double* out, int32_t nshell, gp_energy* energies) {
+  gp_status st = usable(p);
+  if (st != GP_OK) return st;
+  if (!psi || !work || !out) return fail(GP_ERR_ARG, "null argument");
+  if (nshell != p->nshell) return fail(GP_ERR_ARG, "nshell %d != %d", nshell, p->nshell);
+  if ((st = diagnose(p, psi, work)) != GP_OK) return st;
+  memcpy(out, p->h_result + 7, 4 * (size_t)p->nshell * sizeof(double));
+  st = copy_energies(p, energies);
+  for (int i = 0; i < 4 * p->nshell && st == GP_OK; ++i)
+    if (!std::isfinite(out[i])) st = fail(GP_ERR_NONFINITE, "spectrum entry %d is not finite", i);
+  return st;
+}
+
+gp_status gp_structure_fn(gp_plan_t* p, const void* psi, void* work, int32_t p_order, double* out) {
+  gp_status st = usable(p);
+  if (st != GP_OK) return st;
+  if (!psi || !work || !out) return fail(GP_ERR_ARG, "null argument");
+  if (p_order != 2) return fail(GP_ERR_UNSUPPORTED, "structure function order %d (only 2)", p_order);
+  const int n = p->d.n[0];
+  if (p->d.n[1] != n || p->d.n[2] != n) return fail(GP_ERR_UNSUPPORTED, "structure function needs a cubic grid");
+  if (n < 2) return fail(GP_ERR_UNSUPPORTED, "structure function needs n >= 2");
+  void* f = field(p, work, 0);
+  const long div[3] = {1, n, (long)n * n};
+  for (int a = 0; a < 3; ++a) {
+    // F_a(|psi|^2 - 1), natural order along axis a
+    if ((st = pass(p, a, V_FWD_DENSITY, psi, f, nullptr, 0.0, nullptr, 1.0)) != GP_OK) return st;
+    launch_axis_power(p->prec, f, p->ntot, div[a], n, p->pow_blocks, p->pow_chunk,
+                      p->power_part + (size_t)a * p->pow_blocks * n, p->stream);
+    if ((st = check_launch(p)) != GP_OK) return st;
+  }
+  launch_structure_final(p->power_part, (int)p->pow_blocks, n, (double)p->ntot, p->d_result, p->stream);
+  if ((st = check_launch(p)) != GP_OK) return st;
+  HIPCHK(p, hipMemcpyAsync(p->h_result, p->d_result, (n / 2) * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  memcpy(out, p->h_result, (n / 2) * sizeof(double));
+  return GP_OK;
+}
+
+gp_status gp_loss_ekin_i_shells(gp_plan_t* p, const void* psi, void* work, int32_t smin, int32_t smax, double* J,
+                                void* lam) {
+  gp_status st = usable(p);
+  if (st != GP_OK) return st;
+  if (!psi || !work || !J || !lam) return fail(GP_ERR_ARG, "null argument");
+  if (smin < 0 || smax < smin) return fail(GP_ERR_ARG, "bad shell range %d..%d", smin, smax);
+  void* d0 = field(p, work, 0);
+  void* d1 = field(p, work, 1);
+  void* d2 = field(p, work, 2);
+  void* g0 = field(p, work, 3);
+  void* g1 = field(p, work, 4);
+  if ((st = derivatives(p, psi, work, false)) != GP_OK) return st;
+  launch_loss_fields(p->prec, psi, d0, d1, d2, g0, g1, p->ntot, p->d.alpha, p->stream);
+  if ((st = check_launch(p)) != GP_OK) return st;
+  if ((st = fwd3_unnorm(p, g0)) != GP_OK) return st;
+  if ((st = fwd3_unnorm(p, g1)) != GP_OK) return st;
+  launch_loss_spectral(p->prec, g0, g1, p->d.n[0], p->d.n[1], p->d.n[2], smin, smax, p->loss_part, p->field_blocks,
+                       p->stream);
+  if ((st = check_launch(p)) != GP_OK) return st;
+  if ((st = inv3_unnorm(p, g0)) != GP_OK) return st;
+  if ((st = inv3_unnorm(p, g1)) != GP_OK) return st;
+  launch_loss_lambda1(p->prec, psi, d0, d1, d2, g0, g1, lam, p->ntot, p->d.alpha, p->stream);
+  if ((st = check_launch(p)) != GP_OK) return st;
+  // d_j <- d/dj (h_j psi), in place
+  for (int a = 0; a < 3; ++a) {
+    void* f = field(p, work, a);
+    if (p->ax[a].n == 1) {
+      HIPCHK(p, hipMemsetAsync(f, 0, p->ntot * p->S, p->stream));
+      continue;
+    }
+    if ((st = pass(p, a, V_PROP, f, f, p->ax[a].deriv)) != GP_OK) return st;
+  }
+  launch_loss_lambda2(p->prec, lam, d0, d1, d2, p->ntot, p->stream);
+  if ((st = check_launch(p)) != GP_OK) return st;
+  launch_sum_partials(p->loss_part, (int)p->field_blocks, p->d_result, p->stream);
+  if ((st = check_launch(p)) != GP_OK) return st;
+  HIPCHK(p, hipMemcpyAsync(p->h_result, p->d_result, sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  *J = p->h_result[0];
+  if (!std::isfinite(*J)) return fail(GP_ERR_NONFINITE, "loss is not finite");
+  return GP_OK;
+}
+
+gp_status gp_adjoint_step_n(gp_plan_t* p, const void* psi_seg_start, void* lam, int64_t nsteps, void* tape) {
+  gp_status st = usable(p);
+  if (st != GP_OK) return st;
+  if (!psi_seg_start || !lam || !tape) return fail(GP_ERR_ARG, "null argument");
+  if (nsteps < 0) return fail(GP_ERR_ARG, "nsteps must be >= 0");
+  if (p->prec != P_C128) return fail(GP_ERR_UNSUPPORTED, "the adjoint is compiled for complex128 only");
+  if (nsteps == 0) return GP_OK;
+  const size_t sb = p->ntot * p->S;
+  auto slot = [&](int64_t i) { return (void*)((char*)tape + (size_t)i * sb); };
+  const double nl = p->d.beta * p->d.dt;
+  const int c = first_real_axis(p);
+  // forward recompute: phi_0 = L(h) psi_0, phi_{n+1} = L(dt) N(phi_n), stored in the tape
+  {
+    const void* src = psi_seg_start;
+    bool first = true;
+    for (int a = 0; a < 3; ++a) {
+      if (p->ax[a].n == 1) continue;
+      if ((st = pass(p, a, V_PROP, first ? src : slot(0), slot(0), p->ax[a].mult[TAU_H])) != GP_OK) return st;
+      first = false;
+    }
+    if (first) {  // 1x1x1 grid
+      launch_scale_copy(p->prec, src, slot(0), p->ntot, 1.0, p->stream);
+      if ((st = check_launch(p)) != GP_OK) return st;
+    }
+  }
+  for (int64_t s = 0; s + 1 < nsteps; ++s) {
+    if (c < 0) {
+      launch_scale_copy(p->prec, slot(s), slot(s + 1), p->ntot, 1.0, p->stream);
+      launch_nonlinear(p->prec, slot(s + 1), p->ntot, nl, p->stream);
+      if ((st = check_launch(p)) != GP_OK) return st;
+      continue;
+    }
+    for (int a = 0; a < 3; ++a) {
+      if (p->ax[a].n == 1) continue;
+      const bool carrier = (a == c);
+      if ((st = pass(p, a, carrier ? V_PROP_NL : V_PROP, carrier ? slot(s) : slot(s + 1), slot(s + 1),
+                     p->ax[a].mult[TAU_DT], nl)) != GP_OK)
+        return st;
+    }
+  }
+  // backward: lam <- L(-h); then per step n (reverse): N'(phi_n)^dagger fused, L(-dt) or L(-h)
+  if ((st = linear_all(p, lam, TAU_MH, false, 0.0)) != GP_OK) return st;
+  for (int64_t s = nsteps - 1; s >= 0; --s) {
+    const int tau = s > 0 ? TAU_MDT : TAU_MH;
+    if (c < 0) {
+      return fail(GP_ERR_UNSUPPORTED, "adjoint on a 1x1x1 grid");
+    }
+    for (int a = 0; a < 3; ++a) {
+      if (p->ax[a].n == 1) continue;
+      const bool carrier = (a == c);
+      if ((st = pass(p, a, carrier ? V_PROP_ADJ : V_PROP, lam, lam, p->ax[a].mult[tau], nl, carrier ? slot(s) : nullptr)) !=
+          GP_OK)
+        return st;
+    }
+  }
+  return GP_OK;
+}
+
+gp_status gp_phase_grad(gp_plan_t* p, const void* psi0, const void* lam0, double* dJ_dtheta) {
+  gp_status st = usable(p);
+  if (st != GP_OK) return st;
+  if (!psi0 || !lam0 || !dJ_dtheta) return fail(GP_ERR_ARG, "null argument");
+  launch_phase_grad(p->prec, psi0, lam0, dJ_dtheta, p->ntot, p->stream);
+  return check_launch(p);
+}
+
+// ----------------------------------------------------------------- ensemble
+gp_status gp_plan_batch(const gp_desc* runs, int32_t nruns, void* hip_stream, gp_plan_t** out) {
+  if (!out) return fail(GP_ERR_ARG, "null output pointer");
+  *out = nullptr;
+  if (!runs || nruns < 1) return fail(GP_ERR_ARG, "need at least one run");
+  gp_status st;
+  for (int i = 0; i < nruns; ++i) {
+    if ((st = validate_desc(&runs[i])) != GP_OK) return st;
+    if (runs[i].prec != runs[0].prec) return fail(GP_ERR_ARG, "all runs of a batch share one precision");
+  }
+  auto* p = new gp_plan_s();
+  p->is_batch = true;
+  p->prec = runs[0].prec;
+  p->S = p->prec == GP_C128 ? 16 : 8;
+  p->d = runs[0];
+  p->stream = (hipStream_t)hip_stream;
+  bool own_stream = false;
+  if (!p->stream) {            // graph capture needs a non-legacy stream
+    hipError_t e = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) { delete p; return fail(GP_ERR_HIP, "hipStreamCreate: %s", hipGetErrorString(e)); }
+    own_stream = true;
+  }
+  for (int i = 0; i < nruns; ++i) {
+    auto* r = new gp_plan_s();
+    p->runs.push_back(r);
+    if ((st = plan_init(r, &runs[i], p->stream)) != GP_OK) {
+      std::string msg = g_err;
+      p->own_stream = own_stream;
+      plan_free(p);
+      g_err = msg;
+      return st;
+    }
+    // group runs of identical grid shape
+    int g = -1;
+    for (size_t j = 0; j < p->groups.size(); ++j) {
+      const auto* r0 = p->runs[p->groups[j].members[0]];
+      if (r0->d.n[0] == r->d.n[0] && r0->d.n[1] == r->d.n[1] && r0->d.n[2] == r->d.n[2]) g = (int)j;
+    }
+    if (g < 0) { p->groups.push_back({}); g = (int)p->groups.size() - 1; p->groups[g].n = r->d.n[0]; }
+    p->groups[g].members.push_back(i);
+  }
+  p->nshell = p->runs[0]->nshell;
+  p->ntot = p->runs[0]->ntot;
+  p->own_stream = own_stream;
+  *out = p;
+  g_err.clear();
+  return GP_OK;
+}
+
+static gp_status batch_record(gp_plan_s* p, void* const* psis, int64_t nsteps) {
+  gp_status st;
+  const bool back = nsteps < 0;
+  const int64_t n = back ? -nsteps : nsteps;
+  const int th = back ? TAU_MH : TAU_H, tf = back ? TAU_MDT : TAU_DT;
+  // per group: RunPtrs[axis][tau in {h, full}][member]
+  for (auto& g : p->groups) {
+    const size_t m = g.members.size();
+    std::vector<RunPtrs> h(3 * 2 * m);
+    for (int a = 0; a < 3; ++a)
+      for (int t = 0; t < 2; ++t)
+        for (size_t i = 0; i < m; ++i) {
+          gp_plan_s* r = p->runs[g.members[i]];
+          RunPtrs& e = h[(a * 2 + t) * m + i];
+          e.in = psis[g.members[i]];
+          e.out = psis[g.members[i]];
+          e.mult = r->ax[a].mult[t == 0 ? th : tf];
+          e.nl_coef = r->d.beta * (back ? -r->d.dt : r->d.dt);
+        }
+    if (g.nptrs < h.size()) {
+      if (g.d_ptrs) (void)hipFree(g.d_ptrs);
+      g.d_ptrs = nullptr;
+      HIPCHK(p, hipMalloc((void**)&g.d_ptrs, h.size() * sizeof(RunPtrs)));
+      g.nptrs = h.size();
+    }
+    HIPCHK(p, hipMemcpy(g.d_ptrs, h.data(), h.size() * sizeof(RunPtrs), hipMemcpyHostToDevice));
+  }
+  if (p->graph_exec) { (void)hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
+  if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+  HIPCHK(p, hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+  auto grouped = [&](const gp_plan_s::Group& g, int a, int t, int var) -> void {
+    gp_plan_s* r = p->runs[g.members[0]];
+    const Axis& A = r->ax[a];
+    const size_t m = g.members.size();
+    PassArgs args{};
+    args.batch = g.d_ptrs + (a * 2 + t) * m;
+    args.tw = A.tw; args.ksq = A.ksq; args.scale = 1.0;
+    args.npencils = A.npencils; args.inner = A.inner; args.outer = A.outer; args.es = A.es; args.nx = r->d.n[0];
+    A.e->fn[A.kind][var](args, A.blocks, (unsigned)m, p->stream);
+  };
+  for (const auto& g : p->groups) {
+    gp_plan_s* r0 = p->runs[g.members[0]];
+    const int c = first_real_axis(r0);
+    if (c < 0) continue;     // 1x1x1 runs are not batched
+    for (int a = 0; a < 3; ++a) if (r0->ax[a].n > 1) grouped(g, a, 0, V_PROP);
+    for (int64_t s = 0; s < n; ++s)
+      for (int a = 0; a < 3; ++a)
+        if (r0->ax[a].n > 1) grouped(g, a, s + 1 < n ? 1 : 0, a == c ? V_PROP_NL : V_PROP);
+  }
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(p->stream, &graph);
+  if (e != hipSuccess) { p->broken = true; return fail(GP_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e)); }
+  p->graph = graph;
+  HIPCHK(p, hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0));
+  p->graph_key.assign(psis, psis + p->runs.size());
+  p->graph_steps = nsteps;
+  return GP_OK;
+}
+
+gp_status gp_step_n_batch(gp_plan_t* p, void* const* psis, int64_t nsteps) {
+  gp_status st = usable(p);
+  if (st != GP_OK) return st;
+  if (!p->is_batch) return fail(GP_ERR_STATE, "not a batch plan");
+  if (!psis) return fail(GP_ERR_ARG, "null state array");
+  for (size_t i = 0; i < p->runs.size(); ++i)
+    if (!psis[i]) return fail(GP_ERR_ARG, "null state of run %zu", i);
+  if (nsteps == 0) return GP_OK;
+  for (const auto* r : p->runs)
+    if (first_real_axis(r) < 0) return fail(GP_ERR_UNSUPPORTED, "1x1x1 runs cannot be batched");
+  const bool same = p->graph_exec && p->graph_steps == nsteps &&
+                    std::equal(p->graph_key.begin(), p->graph_key.end(), psis);
+  if (!same && (st = batch_record(p, psis, nsteps)) != GP_OK) return st;
+  HIPCHK(p, hipGraphLaunch(p->graph_exec, p->stream));
+  return GP_OK;
+}
+
+gp_status gp_energies_batch(gp_plan_t* p, void* const* psis, void* work, double* out) {
+  gp_status st = usable(p);
+  if (st != GP_OK) return st;
+  if (!p->is_batch) return fail(GP_ERR_STATE, "not a batch plan");
+  if (!psis || !work || !out) return fail(GP_ERR_ARG, "null argument");
+  for (size_t i = 0; i < p->runs.size(); ++i) {
+    if (!psis[i]) return fail(GP_ERR_ARG, "null state of run %zu", i);
+    gp_energy e{};
+    if ((st = diagnose(p->runs[i], psis[i], work)) != GP_OK) { p->broken = p->runs[i]->broken; return st; }
+    if ((st = copy_energies(p->runs[i], &e)) != GP_OK) return st;
+    out[2 * i] = e.mass;
+    out[2 * i + 1] = e.energy;
+  }
+  return GP_OK;
+}
+
+}  // extern "C"
