@@ -1,0 +1,169 @@
+"""Benchmark of the Gross-Pitaevskii split step on one MI355X.
+
+Workload (tg256): 256^3 periodic box, Taylor-Green vortex-lattice ansatz with
+core width xi = 2 (2 pi / 256), alpha beta = 2 (alpha = 0.06942, beta = 28.81),
+dt = 5e-4, energy decomposition and shell spectra every 100 steps, complex128
+(headline) and complex64.  One bench "step" is one pass of the whole hot path:
+100 Strang steps (gp_step_n) followed by the diagnostics (gp_spectra); the
+default 10 timed bench steps are the workload's 1000 time steps.
+
+Printed: one JSON line with the throughput in grid-point.steps/s, the roofline
+of the axis-pass kernel (HIP events over the timed region), the complex64 form
+at its measured energy drift, and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
+WORKLOAD = "tg256"
+DIAG_EVERY = 100
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def run_form(gp, torch, psi0_np, w, prec, steps, warmup, timed=True):
+    """Time `steps` bench steps (100 split steps + diagnostics each) after `warmup`."""
+    n = w["n"]
+    plan = gp.Plan(n, w["alpha"], w["beta"], w["dt"], prec)
+    dt = torch.complex128 if prec == "c128" else torch.complex64
+    psi = torch.from_numpy(psi0_np).to("cuda").to(dt).contiguous()
+    stream = torch.cuda.current_stream()
+    e0 = plan.energies(psi)
+    energies = [e0]
+    for _ in range(warmup):
+        plan.step_n(psi, DIAG_EVERY)
+        plan.spectra(psi)
+    # restart from the initial condition so the timed run is the workload itself
+    psi.copy_(torch.from_numpy(psi0_np).to("cuda").to(dt))
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ev[i][0].record(stream)
+        plan.step_n(psi, DIAG_EVERY)
+        ev[i][1].record(stream)
+        spec, e = plan.spectra(psi)          # synchronizes the stream
+        energies.append(e)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = [a.elapsed_time(b) for a, b in ev]
+    passes_per_call = 3 * (DIAG_EVERY + 1)
+    mean_pass_ms = sum(step_ms) / (passes_per_call * steps)
+    E0 = e0["energy"]
+    N0 = e0["mass"]
+    dE = max(abs(e["energy"] - E0) for e in energies) / E0
+    dN = max(abs(e["mass"] - N0) for e in energies) / N0
+    out = psi.to(torch.complex128).cpu().numpy()
+    return dict(plan=plan, wall=wall, step_ms=step_ms, mean_pass_ms=mean_pass_ms, dE=dE, dN=dN, psi=out,
+                energies=energies, spec=spec)
+
+
+def oracle_sample(psi0_np, w):
+    """The CPU oracle on a bounded sample: one literal Strang step of the same 256^3 field."""
+    from oracle import gp as O
+    t = time.perf_counter()
+    O.strang_step(psi0_np, w["alpha"], w["beta"], w["dt"])
+    dt = time.perf_counter() - t
+    npts = float(psi0_np.size)
+    return {"value": npts / dt, "unit": "grid-point.steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"one literal Strang step (4 3-D FFTs, numpy FP64, single thread) of the 256^3 "
+                      f"tg256 field, {dt:.1f} s on {cpu_model()}; diagnostics (1 per 100 steps) not included",
+            "seconds": dt, "host_cpus": os.cpu_count()}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10, help="timed bench steps (100 split steps + diagnostics each)")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU "
+              "decomposition is a design, not a built path", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import gp_inputs as I
+    import paper_2003_03590_amd as gp
+
+    w = I.WORKLOADS[WORKLOAD]
+    n = w["n"]
+    xi, expo = w["ic"][1]["xi"], w["ic"][1]["exponent"]
+    psi0 = I.tg_psi(n, xi, expo)
+    npts = float(n) ** 3
+
+    f64 = run_form(gp, torch, psi0, w, "c128", a.steps, a.warmup)
+    split_steps = a.steps * DIAG_EVERY
+    value = npts * split_steps / f64["wall"]
+    step_only = npts * split_steps / (sum(f64["step_ms"]) / 1e3)
+    S = 16
+    bytes_per_pass = 2.0 * npts * S
+    achieved = bytes_per_pass / (f64["mean_pass_ms"] / 1e3) / 1e9
+
+    res = {
+        "metric": "grid-point.steps/s (Strang split step incl. diagnostics every 100 steps)",
+        "value": value,
+        "unit": "grid-point.steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": f64["wall"] / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (Taylor-Green ansatz, seedless closed form)",
+        "config": {"workload": "tg256: 256^3 Taylor-Green ansatz psi_4^2, xi=2*(2pi/256), alpha=0.069420, "
+                               "beta=28.810, dt=5e-4, 1000 steps, energy split + shell spectra every 100 steps",
+                   "grid": [n, n, n], "prec": "complex128", "split_steps_timed": split_steps,
+                   "bench_step": "100 Strang steps + gp_spectra"},
+        "value_step_only": step_only,
+        "hbm_gbs_per_split_step": 6.0 * npts * S / (sum(f64["step_ms"]) / 1e3 / split_steps) / 1e9,
+        "bytes_per_split_step_min": 6.0 * npts * S,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "axis_pass (x: fused nonlinear + propagator, y, z: propagator), mean of the three",
+                     "per_launch_bytes": bytes_per_pass, "mean_launch_us": f64["mean_pass_ms"] * 1e3},
+        "drift_f64": {"dE": f64["dE"], "dN": f64["dN"]},
+        "schedule": [f64["plan"].schedule(ax) for ax in range(3)],
+    }
+    if not a.no_fp32:
+        f32 = run_form(gp, torch, psi0, w, "c64", a.steps, a.warmup)
+        v32 = npts * split_steps / f32["wall"]
+        rel = float(np.linalg.norm(f32["psi"] - f64["psi"]) / np.linalg.norm(f64["psi"]))
+        ach32 = 2.0 * npts * 8 / (f32["mean_pass_ms"] / 1e3) / 1e9
+        res["fp32"] = {"value": v32, "ms_per_step": f32["wall"] / a.steps * 1e3, "speedup_vs_f64": v32 / value,
+                       "value_step_only": npts * split_steps / (sum(f32["step_ms"]) / 1e3),
+                       "dE": f32["dE"], "dN": f32["dN"], "rel_l2_psi_vs_f64_gpu": rel,
+                       "axis_pass_gbs": ach32, "axis_pass_frac": ach32 / HBM_PEAK_GBS,
+                       "mean_launch_us": f32["mean_pass_ms"] * 1e3}
+    if not a.no_cpu_baseline:
+        res["cpu_baseline"] = oracle_sample(psi0, w)
+    print(json.dumps(res))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -40,6 +40,29 @@ template <class Real>
 __device__ __forceinline__ Real cabs2(cplx<Real> a) { return a.x * a.x + a.y * a.y; }
 
 // ---------------------------------------------------------------------------
+// Table entries.  complex128 tables hold the FP64 value.  complex64 tables hold
+// the FP64 value as an unevaluated sum hi + lo of two FP32 complex numbers, so
+// the FP32 kernels multiply by a constant accurate to ~1e-14: a constant
+// rounded to FP32 would have |w| != 1 by up to 6e-8, a gain that repeats every
+// pass and accumulates linearly over thousands of passes.
+template <class Real> struct Tab;
+template <> struct alignas(16) Tab<double> { cplx<double> v; };
+template <> struct alignas(16) Tab<float> { cplx<float> hi, lo; };
+
+__device__ __forceinline__ cplx<double> tmul(cplx<double> a, const Tab<double>& t) { return cmul(a, t.v); }
+__device__ __forceinline__ cplx<double> tmulc(cplx<double> a, const Tab<double>& t) { return cmulc(a, t.v); }
+// a * (hi + lo), the small products added first
+__device__ __forceinline__ cplx<float> tmul(cplx<float> a, const Tab<float>& t) {
+  const float sr = a.x * t.lo.x - a.y * t.lo.y, si = a.x * t.lo.y + a.y * t.lo.x;
+  return mk(fmaf(a.x, t.hi.x, fmaf(-a.y, t.hi.y, sr)), fmaf(a.x, t.hi.y, fmaf(a.y, t.hi.x, si)));
+}
+// a * conj(hi + lo)
+__device__ __forceinline__ cplx<float> tmulc(cplx<float> a, const Tab<float>& t) {
+  const float sr = a.x * t.lo.x + a.y * t.lo.y, si = a.y * t.lo.x - a.x * t.lo.y;
+  return mk(fmaf(a.x, t.hi.x, fmaf(a.y, t.hi.y, sr)), fmaf(a.y, t.hi.x, fmaf(-a.x, t.hi.y, si)));
+}
+
+// ---------------------------------------------------------------------------
 // Compile-time cos/sin of 2*pi*m/R.  The angle is reduced exactly in integers
 // to [0, pi/4] and evaluated with a Taylor series in double (error ~1 ulp).
 namespace ct {
@@ -92,9 +115,15 @@ __device__ __forceinline__ cplx<Real> rot(cplx<Real> v) {
     return SGN < 0 ? mk(v.y, -v.x) : mk(-v.y, v.x);
   } else if constexpr (4 * m == 3 * R) {        // exp(SGN i 3pi/2) = -SGN * i
     return SGN < 0 ? mk(-v.y, v.x) : mk(v.y, -v.x);
+  } else if constexpr (sizeof(Real) == 4) {
+    // FP32: constant carried as hi + lo (see Tab<float>)
+    constexpr double cd = Root<m, R, SGN>::c, sd = Root<m, R, SGN>::s;
+    constexpr float ch = float(cd), sh = float(sd);
+    constexpr float cl = float(cd - double(ch)), sl = float(sd - double(sh));
+    const float sr = v.x * cl - v.y * sl, si = v.x * sl + v.y * cl;
+    return mk(fmaf(v.x, ch, fmaf(-v.y, sh, sr)), fmaf(v.x, sh, fmaf(v.y, ch, si)));
   } else {
-    constexpr Real c = Real(Root<m, R, SGN>::c);
-    constexpr Real s = Real(Root<m, R, SGN>::s);
+    constexpr double c = Root<m, R, SGN>::c, s = Root<m, R, SGN>::s;
     return mk(v.x * c - v.y * s, v.x * s + v.y * c);
   }
 }

@@ -40,11 +40,9 @@ struct PassArgs {
   const RunPtrs* batch;    // grouped launch over runs of one size, or null
   const void* in;          // input field (complex, working precision)
   void* out;               // output field (may equal in)
-  const void* mult;        // PROP: multiplier in position order (N_j complex)
-  const void* tw;          // W_N^m = exp(-2 pi i m / N_j), m < N_j
+  const void* mult;        // PROP: multiplier in position order (N_j Tab<Real> entries)
+  const void* tw;          // W_N^m = exp(-2 pi i m / N_j), m < N_j (Tab<Real> entries)
   const void* aux;         // PRO_ADJ_NL: forward state phi at the same points
-  const void* pmx;         // optional per-pencil factors (natural order along x, y) for the
-  const void* pmy;         //   literal 3-D propagator on the z pass; null otherwise
   const double* ksq;       // k_j^2 in position order (kinetic accumulation)
   double* kin_partial;     // per-workgroup partial sum of k_j^2 |F_j v|^2 (or null)
   double nl_coef;          // beta * dt of the nonlinear prologue
@@ -52,7 +50,6 @@ struct PassArgs {
   long npencils;           // number of pencils along this axis
   long inner, outer;       // pencil p starts at (p / inner) * outer + (p % inner)
   long es;                 // element stride along the axis
-  int nx;                  // grid size along x (pencil factor lookup on the z pass)
 };
 
 template <int N_, int T_, int W_, int R0, int R1, int R2>
@@ -139,7 +136,7 @@ __device__ __forceinline__ void exchange(cplx<Real>* lds, cplx<Real>* v, int t, 
 
 // forward DIF stage s: butterfly over digit s, then twiddle W_{L_s}^{lo*k}
 template <class Real, class S, int s>
-__device__ __forceinline__ void fwd_stage(cplx<Real>* v, int t, const cplx<Real>* __restrict__ tw) {
+__device__ __forceinline__ void fwd_stage(cplx<Real>* v, int t, const Tab<Real>* __restrict__ tw) {
   constexpr int R = S::rad(s), B = S::E / R, Ms = S::M(s), Ls = R * Ms, STEP = S::N / Ls;
 #pragma unroll
   for (int j = 0; j < B; ++j) {
@@ -150,7 +147,7 @@ __device__ __forceinline__ void fwd_stage(cplx<Real>* v, int t, const cplx<Real>
     if constexpr (Ms > 1) {
       const int lo = (t + S::T * j) % Ms;
 #pragma unroll
-      for (int k = 1; k < R; ++k) x[k] = cmul(x[k], tw[lo * k * STEP]);
+      for (int k = 1; k < R; ++k) x[k] = tmul(x[k], tw[lo * k * STEP]);
     }
 #pragma unroll
     for (int k = 0; k < R; ++k) v[j + B * k] = x[k];
@@ -159,7 +156,7 @@ __device__ __forceinline__ void fwd_stage(cplx<Real>* v, int t, const cplx<Real>
 
 // inverse of fwd_stage (up to the factor R): conjugate twiddle, then inverse butterfly
 template <class Real, class S, int s>
-__device__ __forceinline__ void inv_stage(cplx<Real>* v, int t, const cplx<Real>* __restrict__ tw) {
+__device__ __forceinline__ void inv_stage(cplx<Real>* v, int t, const Tab<Real>* __restrict__ tw) {
   constexpr int R = S::rad(s), B = S::E / R, Ms = S::M(s), Ls = R * Ms, STEP = S::N / Ls;
 #pragma unroll
   for (int j = 0; j < B; ++j) {
@@ -169,7 +166,7 @@ __device__ __forceinline__ void inv_stage(cplx<Real>* v, int t, const cplx<Real>
     if constexpr (Ms > 1) {
       const int lo = (t + S::T * j) % Ms;
 #pragma unroll
-      for (int k = 1; k < R; ++k) x[k] = cmulc(x[k], tw[lo * k * STEP]);
+      for (int k = 1; k < R; ++k) x[k] = tmulc(x[k], tw[lo * k * STEP]);
     }
     Dft<R, +1, Real>::run(x);
 #pragma unroll
@@ -179,7 +176,7 @@ __device__ __forceinline__ void inv_stage(cplx<Real>* v, int t, const cplx<Real>
 
 template <class Real, class S, int KIND, int s>
 __device__ __forceinline__ void forward_all(cplx<Real>* v, cplx<Real>* lds, int t, int col,
-                                            const cplx<Real>* __restrict__ tw) {
+                                            const Tab<Real>* __restrict__ tw) {
   fwd_stage<Real, S, s>(v, t, tw);
   if constexpr (s + 1 < S::NS) {
     exchange<Real, S, KIND, s, s + 1>(lds, v, t, col);
@@ -189,7 +186,7 @@ __device__ __forceinline__ void forward_all(cplx<Real>* v, cplx<Real>* lds, int 
 
 template <class Real, class S, int KIND, int s>
 __device__ __forceinline__ void inverse_all(cplx<Real>* v, cplx<Real>* lds, int t, int col,
-                                            const cplx<Real>* __restrict__ tw) {
+                                            const Tab<Real>* __restrict__ tw) {
   inv_stage<Real, S, s>(v, t, tw);
   if constexpr (s > 0) {
     exchange<Real, S, KIND, s, s - 1>(lds, v, t, col);
@@ -197,11 +194,12 @@ __device__ __forceinline__ void inverse_all(cplx<Real>* v, cplx<Real>* lds, int 
   }
 }
 
-// nonlinear sub-step S(dt, N): v <- v exp(-i beta (|v|^2 - 1) dt)
+// nonlinear sub-step S(dt, N): v <- v exp(-i beta (|v|^2 - 1) dt), in the working precision
+// (an FP64 factor for FP32 data was measured to change neither mass nor energy drift)
 template <class Real>
-__device__ __forceinline__ cplx<Real> nl_rotate(cplx<Real> v, Real coef) {
+__device__ __forceinline__ cplx<Real> nl_rotate(cplx<Real> v, double coef) {
   Real s, c;
-  sincos_rot(-coef * (cabs2(v) - Real(1)), &s, &c);
+  sincos_rot(-Real(coef) * (cabs2(v) - Real(1)), &s, &c);
   return cmul(v, mk(c, s));
 }
 
@@ -241,7 +239,7 @@ __global__ __launch_bounds__(S::THREADS) void axis_pass(PassArgs a) {
   const long es = a.es;
   const C* __restrict__ in = reinterpret_cast<const C*>(a.in);
   C* __restrict__ out = reinterpret_cast<C*>(a.out);
-  const C* __restrict__ tw = reinterpret_cast<const C*>(a.tw);
+  const Tab<Real>* __restrict__ tw = reinterpret_cast<const Tab<Real>*>(a.tw);
 
   C v[E];
   if (active) {
@@ -254,9 +252,8 @@ __global__ __launch_bounds__(S::THREADS) void axis_pass(PassArgs a) {
 
   if constexpr (MODE != INV) {
     if constexpr (PRO == PRO_NL) {
-      const Real coef = Real(a.nl_coef);
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = nl_rotate(v[e], coef);
+      for (int e = 0; e < E; ++e) v[e] = nl_rotate(v[e], a.nl_coef);
     } else if constexpr (PRO == PRO_ADJ_NL) {
       const C* __restrict__ phi = reinterpret_cast<const C*>(a.aux);
       const Real coef = Real(a.nl_coef);
@@ -304,18 +301,13 @@ __global__ __launch_bounds__(S::THREADS) void axis_pass(PassArgs a) {
           a.kin_partial[blockIdx.x] = s;
         }
       }
-      const C* __restrict__ mult = reinterpret_cast<const C*>(a.mult);
-      C pf = mk(Real(1), Real(0));
-      if (a.pmx) {
-        const long xi = pp % a.nx, yi = pp / a.nx;
-        pf = cmul(reinterpret_cast<const C*>(a.pmx)[xi], reinterpret_cast<const C*>(a.pmy)[yi]);
-      }
+      const Tab<Real>* __restrict__ mult = reinterpret_cast<const Tab<Real>*>(a.mult);
 #pragma unroll
       for (int r = 0; r < S::rad(L); ++r)
 #pragma unroll
         for (int j = 0; j < B; ++j) {
           const int pos = stage_pos<S, L>(t, j, r);
-          v[j + B * r] = cmul(v[j + B * r], cmul(mult[pos], pf));
+          v[j + B * r] = tmul(v[j + B * r], mult[pos]);
         }
       inverse_all<Real, S, KIND, L>(v, lds, t, col, tw);
     } else {  // FWD: reorder to natural frequency order

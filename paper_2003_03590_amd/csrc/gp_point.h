@@ -14,9 +14,9 @@ void launch_diag_fields(int prec, const void* psi, void* f0, void* f1, void* f2,
                         double* partial, unsigned blocks, hipStream_t st);
 void launch_spectral(int prec, const void* F0, const void* F1, const void* F2, int nx, int ny, int nz, double alpha,
                      double beta, int nshell, unsigned blocks, long chunk, double* bins, hipStream_t st);
-void launch_finalize_diag(const double* kin, int nk0, int nk1, int nk2, double w0, double w1, double w2,
-                          const double* field, int nfield, const double* bins, int nbins, int nshell, double alpha,
-                          double beta, double ntot, double* out, hipStream_t st);
+void launch_segsum(const double* in, long len, int nseg, double* out, hipStream_t st);
+void launch_finalize_diag(const double* red, double w0, double w1, double w2, int nshell, double alpha, double beta,
+                          double ntot, double* out, hipStream_t st);
 void launch_loss_fields(int prec, const void* psi, const void* d0, const void* d1, const void* d2, void* f0,
                         void* f1, long n, double alpha, hipStream_t st);
 void launch_loss_spectral(int prec, void* F0, void* F1, int nx, int ny, int nz, int smin, int smax,
@@ -25,10 +25,9 @@ void launch_loss_lambda1(int prec, const void* psi, void* d0, void* d1, void* d2
                          void* lam, long n, double alpha, hipStream_t st);
 void launch_loss_lambda2(int prec, void* lam, const void* e0, const void* e1, const void* e2, long n,
                          hipStream_t st);
-void launch_sum_partials(const double* p, int n, double* out, hipStream_t st);
 void launch_phase_grad(int prec, const void* psi0, const void* lam0, double* out, long n, hipStream_t st);
 void launch_axis_power(int prec, const void* F, long n, long div, int nj, unsigned blocks, long chunk,
                        double* part, hipStream_t st);
-void launch_structure_final(const double* part, int nblk, int nj, double ntot, double* out, hipStream_t st);
+void launch_structure_final(const double* pk, int nj, double ntot, double* out, hipStream_t st);
 
 }  // namespace gpk

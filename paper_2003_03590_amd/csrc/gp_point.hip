@@ -71,12 +71,8 @@ __global__ void k_init_phase(const double* __restrict__ theta, void* psi, long n
 template <class Real>
 __global__ void k_nonlinear(void* psi, long n, double coef) {
   cplx<Real>* p = reinterpret_cast<cplx<Real>*>(psi);
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    const cplx<Real> v = p[i];
-    Real s, c;
-    sincos_rot(Real(-coef) * (cabs2(v) - Real(1)), &s, &c);
-    p[i] = cmul(v, mk(c, s));
-  }
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    p[i] = nl_rotate(p[i], coef);
 }
 
 template <class Real>
@@ -92,10 +88,12 @@ template <class Real>
 __global__ void k_mult3(void* f, int nx, int ny, int nz, const void* mx, const void* my, const void* mz) {
   const long n = (long)nx * ny * nz;
   cplx<Real>* p = reinterpret_cast<cplx<Real>*>(f);
+  const Tab<Real>* tx = reinterpret_cast<const Tab<Real>*>(mx);
+  const Tab<Real>* ty = reinterpret_cast<const Tab<Real>*>(my);
+  const Tab<Real>* tz = reinterpret_cast<const Tab<Real>*>(mz);
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
     const int ix = (int)(i % nx), iy = (int)((i / nx) % ny), iz = (int)(i / ((long)nx * ny));
-    const cplx<Real> m = cmul(cmul(ldc<Real>(mx, ix), ldc<Real>(my, iy)), ldc<Real>(mz, iz));
-    p[i] = cmul(p[i], m);
+    p[i] = tmul(tmul(tmul(p[i], tx[ix]), ty[iy]), tz[iz]);
   }
 }
 
@@ -103,7 +101,7 @@ __global__ void k_mult3(void* f, int nx, int ny, int nz, const void* mx, const v
 // In: psi and its spectral derivatives d0 = d/dx, d1 = d/dy, d2 = d/dz (in f0, f1, f2).
 // Out (in place): f0 = w_x + i w_y, f1 = w_z + i |psi|, f2 = (|psi|^2 - 1) + 0i,
 // w = 2 alpha Im(conj(psi) grad psi)/|psi| (0 where psi = 0).
-// Partials per block: [sum rho, sum (rho-1)^2, sum |w|^2].
+// Partials [quantity][block]: sum rho, sum (rho-1)^2, sum |w|^2.
 template <class Real>
 __global__ __launch_bounds__(256) void k_diag_fields(const void* psi, void* f0, void* f1, void* f2, long n,
                                                      double alpha, double* __restrict__ partial) {
@@ -133,9 +131,9 @@ __global__ __launch_bounds__(256) void k_diag_fields(const void* psi, void* f0, 
   const double s1 = block_sum256(a1.val(), sh);
   const double s2 = block_sum256(a2.val(), sh);
   if (threadIdx.x == 0) {
-    partial[3 * blockIdx.x + 0] = s0;
-    partial[3 * blockIdx.x + 1] = s1;
-    partial[3 * blockIdx.x + 2] = s2;
+    partial[blockIdx.x] = s0;
+    partial[gridDim.x + blockIdx.x] = s1;
+    partial[2 * gridDim.x + blockIdx.x] = s2;
   }
 }
 
@@ -189,37 +187,36 @@ __global__ __launch_bounds__(64) void k_spectral(const void* F0, const void* F1,
     atomicAdd(&bins[3 * nshell + s], eint);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < 4 * nshell; i += 64) bins_partial[(long)blockIdx.x * 4 * nshell + i] = bins[i];
+  for (int i = threadIdx.x; i < 4 * nshell; i += 64) bins_partial[(long)i * gridDim.x + blockIdx.x] = bins[i];
 }
 
-// Final fixed-order reduction of every diagnostic partial (one block of 256).
-// out[0..6] = gp_energy, out[7 ..] = spectra [4][nshell].
-__global__ __launch_bounds__(256) void k_finalize_diag(const double* __restrict__ kin, int nkin0, int nkin1, int nkin2,
-                                                       double kin_w0, double kin_w1, double kin_w2,
-                                                       const double* __restrict__ field, int nfield,
-                                                       const double* __restrict__ bins, int nbins, int nshell,
-                                                       double alpha, double beta, double ntot, double* __restrict__ out) {
-  extern __shared__ double spec[];            // [4][nshell]
-  // spectra: one thread per (row, shell), blocks summed in order
-  for (int q = threadIdx.x; q < 4 * nshell; q += 256) {
-    Neu a;
-    for (int b = 0; b < nbins; ++b) a.add(bins[(long)b * 4 * nshell + q]);
-    spec[q] = a.val();
-    out[7 + q] = spec[q];
-  }
-  __syncthreads();
+// Deterministic segmented sum: out[q] = sum_{b < len} in[q * len + b] for q < nseg.
+// One block of 256 threads per segment: strided Neumaier partials per thread, then
+// a fixed-order tree over the 256 threads (wave butterflies, then waves in order).
+__global__ __launch_bounds__(256) void k_segsum(const double* __restrict__ in, long len, double* __restrict__ out) {
+  __shared__ double sh[4];
+  const double* seg = in + (long)blockIdx.x * len;
+  Neu a;
+  for (long b = threadIdx.x; b < len; b += 256) a.add(seg[b]);
+  const double v = block_sum256(a.val(), sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = v;
+}
+
+// Energies from the reduced sums.  red = [kin_x, kin_y, kin_z, sum rho, sum (rho-1)^2,
+// sum |w|^2, spectra[4][nshell]]; out[0..6] = gp_energy, out[7..] = spectra.
+__global__ __launch_bounds__(256) void k_finalize_diag(const double* __restrict__ red, double kin_w0, double kin_w1,
+                                                       double kin_w2, int nshell, double alpha, double beta,
+                                                       double ntot, double* __restrict__ out) {
+  const double* spec = red + 6;
+  for (int q = threadIdx.x; q < 4 * nshell; q += 256) out[7 + q] = spec[q];
   if (threadIdx.x == 0) {
-    Neu k0, k1, k2, f0, f1, f2, ei, ec, eq;
-    for (int b = 0; b < nkin0; ++b) k0.add(kin[b]);
-    for (int b = 0; b < nkin1; ++b) k1.add(kin[nkin0 + b]);
-    for (int b = 0; b < nkin2; ++b) k2.add(kin[nkin0 + nkin1 + b]);
-    for (int b = 0; b < nfield; ++b) { f0.add(field[3 * b]); f1.add(field[3 * b + 1]); f2.add(field[3 * b + 2]); }
+    Neu ei, ec, eq;
     for (int s = 0; s < nshell; ++s) { ei.add(spec[s]); ec.add(spec[nshell + s]); eq.add(spec[2 * nshell + s]); }
-    const double kin_grad = k0.val() * kin_w0 + k1.val() * kin_w1 + k2.val() * kin_w2;
-    const double e_int = alpha * beta * f1.val() / ntot;
-    out[0] = f0.val() / ntot;                         // mass
+    const double kin_grad = red[0] * kin_w0 + red[1] * kin_w1 + red[2] * kin_w2;
+    const double e_int = alpha * beta * red[4] / ntot;
+    out[0] = red[3] / ntot;                           // mass
     out[1] = 2.0 * alpha * alpha * kin_grad + e_int;  // energy
-    out[2] = 0.5 * f2.val() / ntot;                   // e_kin
+    out[2] = 0.5 * red[5] / ntot;                     // e_kin
     out[3] = ei.val();
     out[4] = ec.val();
     out[5] = eq.val();
@@ -344,14 +341,6 @@ __global__ __launch_bounds__(256) void k_loss_lambda2(void* lam, const void* e0,
   }
 }
 
-__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ p, int n, double* __restrict__ out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    Neu a;
-    for (int i = 0; i < n; ++i) a.add(p[i]);
-    out[0] = a.val();
-  }
-}
-
 template <class Real>
 __global__ void k_phase_grad(const void* psi0, const void* lam0, double* out, long n) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
@@ -380,7 +369,7 @@ __device__ __forceinline__ void axis_power(const void* F, long n, long div, int 
     atomicAdd(&bins[(i / div) % nj], (double)z.x * z.x + (double)z.y * z.y);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < nj; i += 64) part[(long)blockIdx.x * nj + i] = bins[i];
+  for (int i = threadIdx.x; i < nj; i += 64) part[(long)i * gridDim.x + blockIdx.x] = bins[i];
 }
 __global__ __launch_bounds__(64) void k_axis_power_c128(const void* F, long n, long div, int nj, long chunk, double* part) {
   axis_power<double>(F, n, div, nj, chunk, part);
@@ -389,17 +378,10 @@ __global__ __launch_bounds__(64) void k_axis_power_c64(const void* F, long n, lo
   axis_power<float>(F, n, div, nj, chunk, part);
 }
 
-// S(m) = (1/3) sum_j 2/(Ntot N_j) sum_k P_j(k) (1 - cos(2 pi k m / N_j)), m = 1..N/2
-__global__ __launch_bounds__(256) void k_structure_final(const double* __restrict__ part, int nblk, int nj, double ntot,
+// S(m) = (1/3) sum_j 2/(Ntot N_j) sum_k P_j(k) (1 - cos(2 pi k m / N_j)), m = 1..N/2,
+// from the reduced power sums pk[axis][k].
+__global__ __launch_bounds__(256) void k_structure_final(const double* __restrict__ pk, int nj, double ntot,
                                                          double* __restrict__ out) {
-  extern __shared__ double pk[];              // [3][nj]: fixed-order sums of the per-block partials
-  for (int q = threadIdx.x; q < 3 * nj; q += 256) {
-    const int ax = q / nj, k = q % nj;
-    Neu a;
-    for (int b = 0; b < nblk; ++b) a.add(part[((long)ax * nblk + b) * nj + k]);
-    pk[q] = a.val();
-  }
-  __syncthreads();
   for (int m = 1 + threadIdx.x; m <= nj / 2; m += 256) {
     Neu a;
     for (int ax = 0; ax < 3; ++ax)
@@ -448,11 +430,12 @@ void launch_spectral(int prec, const void* F0, const void* F1, const void* F2, i
   else
     hipLaunchKernelGGL(k_spectral<float>, dim3(blocks), dim3(64), sh, st, F0, F1, F2, nx, ny, nz, alpha, beta, nshell, chunk, bins);
 }
-void launch_finalize_diag(const double* kin, int nk0, int nk1, int nk2, double w0, double w1, double w2,
-                          const double* field, int nfield, const double* bins, int nbins, int nshell, double alpha,
-                          double beta, double ntot, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize_diag, dim3(1), dim3(256), sizeof(double) * 4 * (size_t)nshell, st, kin, nk0, nk1, nk2, w0, w1, w2, field, nfield, bins,
-                     nbins, nshell, alpha, beta, ntot, out);
+void launch_segsum(const double* in, long len, int nseg, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_segsum, dim3(nseg), dim3(256), 0, st, in, len, out);
+}
+void launch_finalize_diag(const double* red, double w0, double w1, double w2, int nshell, double alpha, double beta,
+                          double ntot, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize_diag, dim3(1), dim3(256), 0, st, red, w0, w1, w2, nshell, alpha, beta, ntot, out);
 }
 void launch_loss_fields(int prec, const void* psi, const void* d0, const void* d1, const void* d2, void* f0, void* f1,
                         long n, double alpha, hipStream_t st) {
@@ -473,9 +456,6 @@ void launch_loss_lambda2(int prec, void* lam, const void* e0, const void* e1, co
   if (prec == P_C128) hipLaunchKernelGGL(k_loss_lambda2<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, lam, e0, e1, e2, n);
   else hipLaunchKernelGGL(k_loss_lambda2<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, lam, e0, e1, e2, n);
 }
-void launch_sum_partials(const double* p, int n, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, st, p, n, out);
-}
 void launch_phase_grad(int prec, const void* psi0, const void* lam0, double* out, long n, hipStream_t st) {
   if (prec == P_C128) hipLaunchKernelGGL(k_phase_grad<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, psi0, lam0, out, n);
   else hipLaunchKernelGGL(k_phase_grad<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, psi0, lam0, out, n);
@@ -486,8 +466,8 @@ void launch_axis_power(int prec, const void* F, long n, long div, int nj, unsign
   if (prec == P_C128) hipLaunchKernelGGL(k_axis_power_c128, dim3(blocks), dim3(64), sh, st, F, n, div, nj, chunk, part);
   else hipLaunchKernelGGL(k_axis_power_c64, dim3(blocks), dim3(64), sh, st, F, n, div, nj, chunk, part);
 }
-void launch_structure_final(const double* part, int nblk, int nj, double ntot, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_structure_final, dim3(1), dim3(256), sizeof(double) * 3 * (size_t)nj, st, part, nblk, nj, ntot, out);
+void launch_structure_final(const double* pk, int nj, double ntot, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_structure_final, dim3(1), dim3(256), 0, st, pk, nj, ntot, out);
 }
 
 }  // namespace gpk

@@ -125,6 +125,8 @@ struct gp_plan_s {
   unsigned pow_blocks = 0;
   long pow_chunk = 0;
   double* loss_part = nullptr;     // field_blocks
+  double* d_red = nullptr;         // 6 + 4 * nshell reduced sums
+  double* d_pk = nullptr;          // 3 * nmax reduced axis power sums
   double* d_result = nullptr;      // 8 + 4 * nshell
   double* h_result = nullptr;      // pinned mirror
   bool broken = false;
@@ -175,17 +177,24 @@ gp_status dev_alloc(gp_plan_s* p, void** ptr, size_t bytes) {
   return GP_OK;
 }
 
-// upload complex FP64 values in working precision
+// upload a complex FP64 table as Tab<Real> entries (16 B each): the FP64 value for
+// complex128, the FP64 value split into FP32 hi + lo for complex64
 gp_status upload_cplx(gp_plan_s* p, void** dst, const std::vector<double>& reim) {
   const size_t n = reim.size() / 2;
-  gp_status st = dev_alloc(p, dst, n * p->S);
+  gp_status st = dev_alloc(p, dst, n * 16);
   if (st != GP_OK) return st;
   if (p->prec == P_C128) {
     HIPCHK(p, hipMemcpy(*dst, reim.data(), n * 16, hipMemcpyHostToDevice));
   } else {
-    std::vector<float> f(reim.size());
-    for (size_t i = 0; i < reim.size(); ++i) f[i] = (float)reim[i];
-    HIPCHK(p, hipMemcpy(*dst, f.data(), n * 8, hipMemcpyHostToDevice));
+    std::vector<float> f(4 * n);
+    for (size_t i = 0; i < n; ++i) {
+      const float hx = (float)reim[2 * i], hy = (float)reim[2 * i + 1];
+      f[4 * i] = hx;
+      f[4 * i + 1] = hy;
+      f[4 * i + 2] = (float)(reim[2 * i] - (double)hx);
+      f[4 * i + 3] = (float)(reim[2 * i + 1] - (double)hy);
+    }
+    HIPCHK(p, hipMemcpy(*dst, f.data(), n * 16, hipMemcpyHostToDevice));
   }
   return GP_OK;
 }
@@ -298,6 +307,8 @@ gp_status plan_init(gp_plan_s* p, const gp_desc* d, hipStream_t stream) {
     return st;
   if ((st = dev_alloc(p, (void**)&p->d_result, (8 + 4 * (size_t)p->nshell + nmax) * sizeof(double))) != GP_OK)
     return st;
+  if ((st = dev_alloc(p, (void**)&p->d_red, (6 + 4 * (size_t)p->nshell) * sizeof(double))) != GP_OK) return st;
+  if ((st = dev_alloc(p, (void**)&p->d_pk, 3 * (size_t)nmax * sizeof(double))) != GP_OK) return st;
   hipError_t e = hipHostMalloc((void**)&p->h_result, (8 + 4 * (size_t)p->nshell + nmax) * sizeof(double),
                                hipHostMallocDefault);
   if (e != hipSuccess) {
@@ -340,8 +351,7 @@ gp_status usable(const gp_plan_s* p) {
 
 // ----------------------------------------------------------------- pass launch
 gp_status pass(gp_plan_s* p, int a, int var, const void* in, void* out, const void* mult, double nl_coef = 0.0,
-               const void* aux = nullptr, double scale = 1.0, double* kin = nullptr, const void* pmx = nullptr,
-               const void* pmy = nullptr) {
+               const void* aux = nullptr, double scale = 1.0, double* kin = nullptr) {
   Axis& A = p->ax[a];
   if (A.n == 1) {
     // one point along the axis: the transform is the identity and k = 0, so the
@@ -353,9 +363,9 @@ gp_status pass(gp_plan_s* p, int a, int var, const void* in, void* out, const vo
   }
   PassArgs g{};
   g.batch = nullptr;
-  g.in = in; g.out = out; g.mult = mult; g.tw = A.tw; g.aux = aux; g.pmx = pmx; g.pmy = pmy;
+  g.in = in; g.out = out; g.mult = mult; g.tw = A.tw; g.aux = aux;
   g.ksq = A.ksq; g.kin_partial = kin; g.nl_coef = nl_coef; g.scale = scale;
-  g.npencils = A.npencils; g.inner = A.inner; g.outer = A.outer; g.es = A.es; g.nx = p->d.n[0];
+  g.npencils = A.npencils; g.inner = A.inner; g.outer = A.outer; g.es = A.es;
   A.e->fn[A.kind][var](g, A.blocks, 1, p->stream);
   return check_launch(p);
 }
@@ -452,13 +462,22 @@ gp_status diagnose(gp_plan_s* p, const void* psi, void* work) {
   launch_spectral(p->prec, f0, f1, f2, p->d.n[0], p->d.n[1], p->d.n[2], p->d.alpha, p->d.beta, p->nshell,
                   p->spec_blocks, p->spec_chunk, p->bins_part, p->stream);
   if ((st = check_launch(p)) != GP_OK) return st;
+  // fixed-order reductions of every partial into red = [kin_x, kin_y, kin_z, field[3], spectra[4][nshell]]
   const double nt = (double)p->ntot;
-  const int nk0 = p->ax[0].n > 1 ? (int)p->ax[0].blocks : 0;
-  const int nk1 = p->ax[1].n > 1 ? (int)p->ax[1].blocks : 0;
-  const int nk2 = p->ax[2].n > 1 ? (int)p->ax[2].blocks : 0;
-  launch_finalize_diag(p->kin_part, nk0, nk1, nk2, 1.0 / (nt * p->ax[0].n), 1.0 / (nt * p->ax[1].n),
-                       1.0 / (nt * p->ax[2].n), p->field_part, (int)p->field_blocks, p->bins_part,
-                       (int)p->spec_blocks, p->nshell, p->d.alpha, p->d.beta, nt, p->d_result, p->stream);
+  double* red = p->d_red;
+  double* kp = p->kin_part;
+  for (int a = 0; a < 3; ++a) {
+    if (p->ax[a].n > 1) {
+      launch_segsum(kp, p->ax[a].blocks, 1, red + a, p->stream);
+      kp += p->ax[a].blocks;
+    } else {
+      HIPCHK(p, hipMemsetAsync(red + a, 0, sizeof(double), p->stream));
+    }
+  }
+  launch_segsum(p->field_part, p->field_blocks, 3, red + 3, p->stream);
+  launch_segsum(p->bins_part, p->spec_blocks, 4 * p->nshell, red + 6, p->stream);
+  launch_finalize_diag(red, 1.0 / (nt * p->ax[0].n), 1.0 / (nt * p->ax[1].n), 1.0 / (nt * p->ax[2].n), p->nshell,
+                       p->d.alpha, p->d.beta, nt, p->d_result, p->stream);
   if ((st = check_launch(p)) != GP_OK) return st;
   const size_t bytes = (7 + 4 * (size_t)p->nshell) * sizeof(double);
   HIPCHK(p, hipMemcpyAsync(p->h_result, p->d_result, bytes, hipMemcpyDeviceToHost, p->stream));
@@ -679,7 +698,9 @@ gp_status gp_structure_fn(gp_plan_t* p, const void* psi, void* work, int32_t p_o
                       p->power_part + (size_t)a * p->pow_blocks * n, p->stream);
     if ((st = check_launch(p)) != GP_OK) return st;
   }
-  launch_structure_final(p->power_part, (int)p->pow_blocks, n, (double)p->ntot, p->d_result, p->stream);
+  // power_part = [axis][k][block] -> reduced pk[axis][k] (in d_red, which holds >= 3 n doubles)
+  launch_segsum(p->power_part, p->pow_blocks, 3 * n, p->d_pk, p->stream);
+  launch_structure_final(p->d_pk, n, (double)p->ntot, p->d_result, p->stream);
   if ((st = check_launch(p)) != GP_OK) return st;
   HIPCHK(p, hipMemcpyAsync(p->h_result, p->d_result, (n / 2) * sizeof(double), hipMemcpyDeviceToHost, p->stream));
   HIPCHK(p, hipStreamSynchronize(p->stream));
@@ -721,7 +742,7 @@ gp_status gp_loss_ekin_i_shells(gp_plan_t* p, const void* psi, void* work, int32
   }
   launch_loss_lambda2(p->prec, lam, d0, d1, d2, p->ntot, p->stream);
   if ((st = check_launch(p)) != GP_OK) return st;
-  launch_sum_partials(p->loss_part, (int)p->field_blocks, p->d_result, p->stream);
+  launch_segsum(p->loss_part, p->field_blocks, 1, p->d_result, p->stream);
   if ((st = check_launch(p)) != GP_OK) return st;
   HIPCHK(p, hipMemcpyAsync(p->h_result, p->d_result, sizeof(double), hipMemcpyDeviceToHost, p->stream));
   HIPCHK(p, hipStreamSynchronize(p->stream));
@@ -882,7 +903,7 @@ static gp_status batch_record(gp_plan_s* p, void* const* psis, int64_t nsteps) {
     PassArgs args{};
     args.batch = g.d_ptrs + (a * 2 + t) * m;
     args.tw = A.tw; args.ksq = A.ksq; args.scale = 1.0;
-    args.npencils = A.npencils; args.inner = A.inner; args.outer = A.outer; args.es = A.es; args.nx = r->d.n[0];
+    args.npencils = A.npencils; args.inner = A.inner; args.outer = A.outer; args.es = A.es;
     A.e->fn[A.kind][var](args, A.blocks, (unsigned)m, p->stream);
   };
   for (const auto& g : p->groups) {
