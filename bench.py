@@ -76,6 +76,45 @@ def run_form(gp, torch, psi0_np, w, prec, steps, warmup, timed=True):
                 energies=energies, spec=spec)
 
 
+def passes_mode(gp, torch, spec, reps):
+    """Each axis pass (propagator sub-step S(s, L_j)) `reps` times on a random
+    N^3 field, then `reps` device copies of the same bytes (calibration of the
+    FETCH_SIZE / WRITE_SIZE counters); prints one JSON line of event timings."""
+    n, prec = spec.split(":")
+    n = int(n)
+    plan = gp.Plan(n, 0.05, 40.0, 1e-3, prec)
+    dt = torch.complex128 if prec == "c128" else torch.complex64
+    S = 16 if prec == "c128" else 8
+    psi = torch.randn(n, n, n, dtype=dt, device="cuda")
+    st = torch.cuda.current_stream()
+    out = {"n": n, "prec": prec, "bytes_per_launch": 2 * n ** 3 * S,
+           "schedule": [plan.schedule(ax) for ax in range(3)]}
+    for ax in range(3):
+        plan.substep_linear(psi, ax, 1e-3)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        for _ in range(reps):
+            plan.substep_linear(psi, ax, 1e-3)
+        b.record(st)
+        torch.cuda.synchronize()
+        us = a.elapsed_time(b) / reps * 1e3
+        out[f"axis{ax}_us"] = us
+        out[f"axis{ax}_GBs"] = 2 * n ** 3 * S / us / 1e3
+    x = torch.empty_like(psi)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    for _ in range(reps):
+        x.copy_(psi)
+    b.record(st)
+    torch.cuda.synchronize()
+    us = a.elapsed_time(b) / reps * 1e3
+    out["copy_us"] = us
+    out["copy_GBs"] = 2 * n ** 3 * S / us / 1e3
+    print(json.dumps(out))
+    return 0
+
+
 def oracle_sample(psi0_np, w):
     """The CPU oracle on a bounded sample: one literal Strang step of the same 256^3 field."""
     from oracle import gp as O
@@ -96,6 +135,10 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--passes", default=None, metavar="N:PREC",
+                    help="profiling mode: time each axis pass alone on an N^3 field (PREC c128|c64) "
+                         "and one device copy of the same bytes, then exit")
+    ap.add_argument("--reps", type=int, default=5)
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU "
@@ -107,6 +150,9 @@ def main(argv=None):
 
     import gp_inputs as I
     import paper_2003_03590_amd as gp
+
+    if a.passes:
+        return passes_mode(gp, torch, a.passes, a.reps)
 
     w = I.WORKLOADS[WORKLOAD]
     n = w["n"]

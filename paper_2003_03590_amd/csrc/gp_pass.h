@@ -69,9 +69,31 @@ struct Sched {
   }
   static_assert(valid(), "inconsistent FFT schedule");
   static constexpr int THREADS = T * W;
-  // LDS layout: CONTIG [col][pos + pad], STRIDED [pos][col]
-  static constexpr int CPAD = N + N / 16;
-  static constexpr int LDS_ELEMS = (NS > 1) ? W * CPAD : 1;
+  static constexpr int RL = rad(NS > 0 ? NS - 1 : 0);     // radix of the last stage
+};
+
+// LDS layout of the stage exchanges (SZ = bytes per element).
+//   CONTIG  [col][pos + pos/RL + pad]: one pad element every RL positions spreads the
+//           stride-RL accesses of the last stage over the banks; the column pitch is
+//           128 B modulo 256 B so two neighbouring columns use different bank halves.
+//   STRIDED [pos + pos/RL][col]: one pad row every RL rows, for the same reason.
+template <class S, int SZ, int KIND>
+struct Lds {
+  static constexpr int PADN = S::N + S::N / S::RL;
+  static constexpr int cpitch() {
+    int c = PADN;
+    if (128 % SZ == 0) {
+      const int mod = 256 / SZ, want = 128 / SZ;
+      while (c % mod != want) ++c;
+    }
+    return c;
+  }
+  static constexpr int CP = cpitch();
+  static constexpr int ELEMS = (S::NS > 1) ? (KIND == CONTIG ? S::W * CP : PADN * S::W) : 1;
+  static __device__ __forceinline__ int addr(int pos, int col) {
+    if constexpr (KIND == CONTIG) return col * CP + pos + pos / S::RL;
+    else return (pos + pos / S::RL) * S::W + col;
+  }
 };
 
 // position held by register (j + B*r) of thread t at stage s
@@ -92,10 +114,9 @@ __device__ __forceinline__ int freq_pos(int k) {
   return p;
 }
 
-template <class S, int KIND>
+template <class Real, class S, int KIND>
 __device__ __forceinline__ int lds_addr(int pos, int col) {
-  if constexpr (KIND == CONTIG) return col * S::CPAD + pos + (pos >> 4);
-  else return pos * S::W + col;
+  return Lds<S, (int)sizeof(cplx<Real>), KIND>::addr(pos, col);
 }
 
 // layout ids for exchanges: 0..NS-1 = stage layouts, -1 = natural frequency layout
@@ -103,26 +124,26 @@ template <class Real, class S, int KIND, int L>
 __device__ __forceinline__ void put(cplx<Real>* lds, const cplx<Real>* v, int t, int col) {
   if constexpr (L < 0) {
 #pragma unroll
-    for (int e = 0; e < S::E; ++e) lds[lds_addr<S, KIND>(freq_pos<S>(t + S::T * e), col)] = v[e];
+    for (int e = 0; e < S::E; ++e) lds[lds_addr<Real, S, KIND>(freq_pos<S>(t + S::T * e), col)] = v[e];
   } else {
     constexpr int B = S::E / S::rad(L);
 #pragma unroll
     for (int r = 0; r < S::rad(L); ++r)
 #pragma unroll
-      for (int j = 0; j < B; ++j) lds[lds_addr<S, KIND>(stage_pos<S, L>(t, j, r), col)] = v[j + B * r];
+      for (int j = 0; j < B; ++j) lds[lds_addr<Real, S, KIND>(stage_pos<S, L>(t, j, r), col)] = v[j + B * r];
   }
 }
 template <class Real, class S, int KIND, int L>
 __device__ __forceinline__ void get(const cplx<Real>* lds, cplx<Real>* v, int t, int col) {
   if constexpr (L < 0) {
 #pragma unroll
-    for (int e = 0; e < S::E; ++e) v[e] = lds[lds_addr<S, KIND>(freq_pos<S>(t + S::T * e), col)];
+    for (int e = 0; e < S::E; ++e) v[e] = lds[lds_addr<Real, S, KIND>(freq_pos<S>(t + S::T * e), col)];
   } else {
     constexpr int B = S::E / S::rad(L);
 #pragma unroll
     for (int r = 0; r < S::rad(L); ++r)
 #pragma unroll
-      for (int j = 0; j < B; ++j) v[j + B * r] = lds[lds_addr<S, KIND>(stage_pos<S, L>(t, j, r), col)];
+      for (int j = 0; j < B; ++j) v[j + B * r] = lds[lds_addr<Real, S, KIND>(stage_pos<S, L>(t, j, r), col)];
   }
 }
 
@@ -221,7 +242,7 @@ template <class Real, class S, int KIND, int MODE, int PRO>
 __global__ __launch_bounds__(S::THREADS) void axis_pass(PassArgs a) {
   using C = cplx<Real>;
   constexpr int T = S::T, W = S::W, E = S::E;
-  __shared__ C lds[S::LDS_ELEMS];
+  __shared__ C lds[Lds<S, (int)sizeof(C), KIND>::ELEMS];
   __shared__ double red[S::THREADS / 64 + 1];
 
   if (a.batch) {                          // uniform per workgroup
@@ -230,9 +251,23 @@ __global__ __launch_bounds__(S::THREADS) void axis_pass(PassArgs a) {
   }
   const int tid = threadIdx.x;
   int t, col;
-  if constexpr (KIND == CONTIG) { t = tid % T; col = tid / T; }
-  else { col = tid % W; t = tid / W; }
-  const long p = (long)blockIdx.x * W + col;
+  if constexpr (KIND == CONTIG) {
+    // TL consecutive points of one pencil form a 128-byte segment; a wavefront
+    // covers several pencils per load instruction (spreads requests over channels)
+    constexpr int TL = (T * (int)sizeof(C) <= 128) ? T : 128 / (int)sizeof(C);
+    t = tid % TL + TL * (tid / (TL * W));
+    col = (tid / TL) % W;
+  } else {
+    col = tid % W;
+    t = tid / W;
+  }
+  // XCD-aware tile order: workgroups are dispatched round-robin over the 8 XCDs;
+  // give each XCD a contiguous run of tiles so tiles that share cache lines meet
+  // in the same L2.
+  const unsigned G = gridDim.x, b = blockIdx.x;
+  const unsigned nfull = G / 8, rem = G % 8, xcd = b % 8;
+  const unsigned tile = xcd * nfull + (xcd < rem ? xcd : rem) + b / 8;
+  const long p = (long)tile * W + col;
   const bool active = p < a.npencils;
   const long pp = active ? p : 0;
   const long base = (pp / a.inner) * a.outer + (pp % a.inner);

@@ -13,7 +13,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/gp.h"
+#include "gp.h"
 #include "gp_point.h"
 
 namespace gpk {
