@@ -1,0 +1,113 @@
+"""Full-size checks of the adjoint (128^3) and ensemble (48 runs) workloads."""
+import math
+
+import numpy as np
+import pytest
+
+import gp_inputs as I
+from oracle import gp as O
+from oracle import adjoint as OA
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _loss_forward(gp, plan, theta_t, steps, smin, smax):
+    psi = plan.init_phase(theta_t)
+    plan.step_n(psi, steps)
+    J, _ = plan.loss_ekin_i_shells(psi, smin, smax)
+    return J
+
+
+def test_adjoint_workload_128_fd_16_directions():
+    """128^3 complex128, alpha = 0.05, beta = 40, dt = 1e-3, 400 steps, SRP |k| <= 6
+    seed 2, J = E_kin^i over shells 4..12 at the final time, checkpoints every 20
+    steps: the adjoint gradient against central differences (h = 1e-6) along 16
+    band-limited random directions (seeds 1000..1015) to 1e-6 relative."""
+    import paper_2003_03590_amd as gp
+    w = I.WORKLOADS["adj128"]
+    n, steps = w["n"], w["steps"]
+    theta = I.srp_fourier_theta(n, w["ic"][1]["K"], w["ic"][1]["seed"])
+    plan = gp.Plan(n, w["alpha"], w["beta"], w["dt"], "c128")
+    th = torch.from_numpy(theta).to(DEV).requires_grad_(True)
+    psi = gp.evolve(th, plan, steps, ckpt=w["ckpt"])
+    J = gp.ekin_i_shells(psi, plan, w["smin"], w["smax"])
+    J.backward()
+    g = th.grad.detach()
+    assert abs(float(g.sum())) < 1e-9 * float(g.abs().sum())        # global phase invariance
+    h = w["fd_h"]
+    worst = 0.0
+    for i in range(w["fd_dirs"]):
+        d = torch.from_numpy(I.srp_fourier_theta(n, 6, w["fd_seed0"] + i)).to(DEV)
+        Jp = _loss_forward(gp, plan, th.detach() + h * d, steps, w["smin"], w["smax"])
+        Jm = _loss_forward(gp, plan, th.detach() - h * d, steps, w["smin"], w["smax"])
+        fd = (Jp - Jm) / (2 * h)
+        ad = float((g * d).sum())
+        worst = max(worst, abs(fd - ad) / abs(fd))
+    print(f"J = {J.item():.10e}, worst FD relative difference {worst:.2e}")
+    assert worst < 1e-6
+
+
+def test_adjoint_cpu_reference_gradient_32():
+    """The same loss at 32^3 over 50 steps: the GPU gradient against the oracle's."""
+    import paper_2003_03590_amd as gp
+    n, alpha, beta, dt, steps = 32, 6.4 / 32, 32 / 3.2, 1e-3, 50
+    theta = I.srp_fourier_theta(n, 6, 2)
+    plan = gp.Plan(n, alpha, beta, dt, "c128")
+    th = torch.from_numpy(theta).to(DEV).requires_grad_(True)
+    J = gp.ekin_i_shells(gp.evolve(th, plan, steps, ckpt=20), plan, 4, 12)
+    J.backward()
+    Jr, gr, _ = OA.gradient_theta(theta, alpha, beta, dt, steps, 4, 12)
+    g = th.grad.cpu().numpy()
+    assert abs(J.item() - Jr) < 1e-11 * Jr
+    assert np.abs(g - gr).max() < 1e-9 * np.abs(gr).max()
+
+
+def _ensemble_inputs(runs, K):
+    return [np.exp(1j * I.srp_fourier_theta(r["n"], K, r["seed"])) for r in runs]
+
+
+def test_ensemble_workload_48_runs():
+    """48 smoothed-random-phase runs (32 at 64^3, 16 at 96^3), complex64, dt = 1e-3,
+    300 steps in one graph launch: every run against its own complex128 run, and
+    per-run mass/energy drift stated."""
+    import paper_2003_03590_amd as gp
+    w = I.WORKLOADS["ens48"]
+    runs = [dict(r, dt=w["dt"]) for r in w["runs"]]
+    init = _ensemble_inputs(runs, w["K"])
+    bp = gp.BatchPlan(runs, "c64")
+    states = [torch.from_numpy(a).to(DEV).to(torch.complex64).contiguous() for a in init]
+    e0 = bp.energies(states)
+    bp.step_n(states, w["steps"])
+    e1 = bp.energies(states)
+    dN = np.abs(e1[:, 0] - e0[:, 0]) / e0[:, 0]
+    dE = np.abs(e1[:, 1] - e0[:, 1]) / e0[:, 1]
+    rels = []
+    for i, r in enumerate(runs):
+        p = gp.Plan(r["n"], r["alpha"], r["beta"], r["dt"], "c128")
+        ref = torch.from_numpy(init[i]).to(DEV).contiguous()
+        p.step_n(ref, w["steps"])
+        a, b = states[i].to(torch.complex128), ref
+        rels.append(float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)))
+        p.close()
+    print(f"ensemble: max dN {dN.max():.2e}, max dE {dE.max():.2e}, max rel-L2 vs c128 {max(rels):.2e}")
+    assert dN.max() < 1e-5 and dE.max() < 1e-4
+    assert max(rels) < 1e-4
+
+
+def test_ensemble_run_against_oracle():
+    """One 64^3 and one 96^3 member of the ensemble for 20 steps against the
+    FP64 oracle (complex64 tolerance)."""
+    import paper_2003_03590_amd as gp
+    w = I.WORKLOADS["ens48"]
+    runs = [dict(w["runs"][0], dt=w["dt"]), dict(w["runs"][32], dt=w["dt"])]
+    init = _ensemble_inputs(runs, w["K"])
+    bp = gp.BatchPlan(runs, "c64")
+    states = [torch.from_numpy(a).to(DEV).to(torch.complex64).contiguous() for a in init]
+    bp.step_n(states, 20)
+    for i, r in enumerate(runs):
+        ref = O.evolve(init[i].astype(np.complex64).astype(np.complex128), r["alpha"], r["beta"], r["dt"], 20,
+                       engine="dft")
+        got = states[i].to(torch.complex128).cpu().numpy()
+        assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 5e-6
