@@ -178,9 +178,19 @@ GP_API const char* gp_last_error(void);
 GP_API const char* gp_schedule_name(const gp_plan_t* p, int32_t axis);
 
 /* Number of compiled schedule variants for an axis length and precision, and
- * selection of one of them for an axis of a plan (autotuning). */
+ * selection of one of them for an axis of a plan.  Selecting rebuilds that
+ * axis's tables (their order follows the schedule's radices); synchronizes. */
 GP_API int32_t gp_variant_count(int32_t n, int32_t prec);
 GP_API gp_status gp_select_variant(gp_plan_t* p, int32_t axis, int32_t variant);
+
+/* Autotuner: for every axis of the plan (every size group of a batch plan),
+ * time `reps` launches of each compiled schedule variant on `scratch` (dev, one
+ * state of the plan's largest run; its contents are overwritten) with HIP
+ * events, and keep the fastest.  cache_path (may be NULL): a JSON file of
+ * earlier choices keyed by GPU architecture, precision, grid shape and axis;
+ * cached choices are applied without timing and new ones are added.
+ * Synchronizes.  A batch plan re-records its graph on the next step call. */
+GP_API gp_status gp_autotune(gp_plan_t* p, void* scratch, int32_t reps, const char* cache_path);
 
 #ifdef __cplusplus
 }

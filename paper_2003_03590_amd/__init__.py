@@ -111,6 +111,13 @@ class Plan:
     def select_variant(self, axis: int, variant: int):
         _check(lib().gp_select_variant(self._h, axis, variant))
 
+    def autotune(self, reps: int = 5, cache: str | None = None):
+        """Time every compiled schedule of each axis and keep the fastest."""
+        scratch = _torch().zeros(self.shape, dtype=self.dtype, device=self.device)
+        _check(lib().gp_autotune(self._h, C.c_void_p(_ptr(scratch)), int(reps),
+                                 cache.encode() if cache else None))
+        return [self.schedule(a) for a in range(3)]
+
     # ---------------------------------------------------------------- method
     def init_phase(self, theta, out=None):
         torch = _torch()
@@ -230,6 +237,14 @@ class BatchPlan:
     def step_n(self, states, nsteps: int):
         _check(lib().gp_step_n_batch(self._h, self._ptrs(states), int(nsteps)))
         return states
+
+    def autotune(self, reps: int = 5, cache: str | None = None):
+        """Autotune each size group on a scratch state of the largest run."""
+        torch = _torch()
+        big = max(self.shapes, key=lambda s: s[0] * s[1] * s[2])
+        scratch = torch.zeros(big, dtype=self.dtype, device=self.device)
+        _check(lib().gp_autotune(self._h, C.c_void_p(scratch.data_ptr()), int(reps),
+                                 cache.encode() if cache else None))
 
     def energies(self, states):
         torch = _torch()

@@ -60,6 +60,7 @@ SIGNATURES = {
     "gp_schedule_name": (C.c_char_p, [P, C.c_int32]),
     "gp_variant_count": (C.c_int32, [C.c_int32, C.c_int32]),
     "gp_select_variant": (ST, [P, C.c_int32, C.c_int32]),
+    "gp_autotune": (ST, [P, P, C.c_int32, C.c_char_p]),
 }
 
 

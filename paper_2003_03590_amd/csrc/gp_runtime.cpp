@@ -958,4 +958,141 @@ gp_status gp_energies_batch(gp_plan_t* p, void* const* psis, void* work, double*
   return GP_OK;
 }
 
+// ----------------------------------------------------------------- autotuner
+// Cache: a flat JSON object {"<arch>/<prec>/<nx>x<ny>x<nz>/a<axis>": variant, ...}.
+static std::map<std::string, int> read_cache(const char* path) {
+  std::map<std::string, int> m;
+  if (!path || !*path) return m;
+  FILE* f = fopen(path, "r");
+  if (!f) return m;
+  std::string txt;
+  char buf[4096];
+  size_t k;
+  while ((k = fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, k);
+  fclose(f);
+  size_t i = 0;
+  while ((i = txt.find('"', i)) != std::string::npos) {
+    const size_t j = txt.find('"', i + 1);
+    if (j == std::string::npos) break;
+    const std::string key = txt.substr(i + 1, j - i - 1);
+    size_t c = txt.find(':', j);
+    if (c == std::string::npos) break;
+    m[key] = atoi(txt.c_str() + c + 1);
+    i = txt.find_first_of(",}", c);
+    if (i == std::string::npos) break;
+  }
+  return m;
+}
+
+static void write_cache(const char* path, const std::map<std::string, int>& m) {
+  if (!path || !*path) return;
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) return;
+  fprintf(f, "{\n");
+  size_t n = 0;
+  for (const auto& kv : m) fprintf(f, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++n < m.size() ? "," : "");
+  fprintf(f, "}\n");
+  fclose(f);
+  rename(tmp.c_str(), path);
+}
+
+static std::string arch_name() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return "unknown";
+  hipDeviceProp_t pr;
+  if (hipGetDeviceProperties(&pr, dev) != hipSuccess) return "unknown";
+  std::string a = pr.gcnArchName;
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+static std::string tune_key(const std::string& arch, const gp_plan_s* p, int axis) {
+  char b[160];
+  snprintf(b, sizeof b, "%s/%s/%dx%dx%d/a%d", arch.c_str(), p->prec == P_C128 ? "c128" : "c64", p->d.n[0], p->d.n[1],
+           p->d.n[2], axis);
+  return b;
+}
+
+// time `reps` in-place propagator passes of the selected schedule (microseconds per launch)
+static gp_status time_axis(gp_plan_s* p, int axis, void* scratch, int reps, double* us) {
+  hipEvent_t a, b;
+  HIPCHK(p, hipEventCreate(&a));
+  HIPCHK(p, hipEventCreate(&b));
+  gp_status st = pass(p, axis, V_PROP, scratch, scratch, p->ax[axis].mult[TAU_DT]);
+  if (st == GP_OK) {
+    (void)hipEventRecord(a, p->stream);
+    for (int r = 0; r < reps && st == GP_OK; ++r) st = pass(p, axis, V_PROP, scratch, scratch, p->ax[axis].mult[TAU_DT]);
+    (void)hipEventRecord(b, p->stream);
+  }
+  float ms = 0.f;
+  if (st == GP_OK) {
+    hipError_t e = hipEventSynchronize(b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    if (e != hipSuccess) { p->broken = true; st = fail(GP_ERR_HIP, "event timing: %s", hipGetErrorString(e)); }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  *us = 1e3 * ms / std::max(1, reps);
+  return st;
+}
+
+static gp_status tune_plan(gp_plan_s* p, void* scratch, int reps, std::map<std::string, int>& cache,
+                           const std::string& arch, int chosen[3]) {
+  gp_status st;
+  for (int a = 0; a < 3; ++a) {
+    chosen[a] = 0;
+    if (p->ax[a].n == 1) continue;
+    const std::string key = tune_key(arch, p, a);
+    auto it = cache.find(key);
+    if (it != cache.end() && find_entry(p->ax[a].n, p->prec, it->second)) {
+      chosen[a] = it->second;
+      if ((st = gp_select_variant(p, a, it->second)) != GP_OK) return st;
+      continue;
+    }
+    const int nv = gp_variant_count(p->ax[a].n, p->prec);
+    double best = 1e300;
+    int bestv = 0;
+    for (int v = 0; v < nv; ++v) {
+      if (!find_entry(p->ax[a].n, p->prec, v)) continue;
+      if ((st = gp_select_variant(p, a, v)) != GP_OK) return st;
+      double us = 0;
+      if ((st = time_axis(p, a, scratch, reps, &us)) != GP_OK) return st;
+      if (us < best) { best = us; bestv = v; }
+    }
+    if ((st = gp_select_variant(p, a, bestv)) != GP_OK) return st;
+    cache[key] = bestv;
+    chosen[a] = bestv;
+  }
+  return GP_OK;
+}
+
+gp_status gp_autotune(gp_plan_t* p, void* scratch, int32_t reps, const char* cache_path) {
+  gp_status st = usable(p);
+  if (st != GP_OK) return st;
+  if (!scratch) return fail(GP_ERR_ARG, "null scratch state");
+  if (reps < 1) return fail(GP_ERR_ARG, "reps must be >= 1");
+  auto cache = read_cache(cache_path);
+  const std::string arch = arch_name();
+  if (!p->is_batch) {
+    int chosen[3];
+    if ((st = tune_plan(p, scratch, reps, cache, arch, chosen)) != GP_OK) return st;
+  } else {
+    for (auto& g : p->groups) {
+      gp_plan_s* r0 = p->runs[g.members[0]];
+      int chosen[3];
+      if ((st = tune_plan(r0, scratch, reps, cache, arch, chosen)) != GP_OK) return st;
+      for (size_t i = 1; i < g.members.size(); ++i)
+        for (int a = 0; a < 3; ++a)
+          if ((st = gp_select_variant(p->runs[g.members[i]], a, chosen[a])) != GP_OK) return st;
+    }
+    // kernels and tables changed: the recorded graph is stale
+    if (p->graph_exec) { (void)hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
+    if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+    p->graph_steps = 0;
+  }
+  write_cache(cache_path, cache);
+  return GP_OK;
+}
+
 }  // extern "C"

@@ -228,3 +228,69 @@ def test_errors_are_reported():
         plan.step_n(torch.zeros((8, 8, 4), dtype=torch.complex128, device=DEV), 1)
     with pytest.raises(gp.GPError):
         gp.Plan(10, 1.0, 1.0, 0.01)
+
+
+def _variants(n, prec):
+    import paper_2003_03590_amd as gp
+    return int(gp.lib().gp_variant_count(n, 0 if prec == "c128" else 1))
+
+
+VARIANT_CASES = [(n, p) for n in (64, 96, 128, 256, 512, 1024) for p in ("c128", "c64")]
+
+
+@pytest.mark.parametrize("n,prec", VARIANT_CASES, ids=lambda v: str(v))
+def test_every_schedule_variant(n, prec):
+    """Each compiled schedule of a length is its own kernel: sub-steps on each
+    axis, a forward/inverse 3-D transform and the diagnostics, per variant."""
+    from oracle.fft import fft3
+    nv = _variants(n, prec)
+    assert nv >= 1
+    tol = TOL[prec] * max(1, math.log2(n))
+    for v in range(nv):
+        for axis in range(3):
+            shape = [6, 4, 2]
+            shape[axis] = n
+            nx, ny, nz = shape
+            psi0 = I.random_field((nz, ny, nx), seed=n + v + axis)
+            plan = _plan(tuple(shape), 0.21, 1.7, 0.01, prec)
+            try:
+                plan.select_variant(axis, v)
+            except Exception:
+                plan.close()
+                continue           # this variant exists for another precision only
+            psi = _to_dev(psi0, prec)
+            plan.substep_linear(psi, axis, 0.03)
+            ref = O.linear_substep_axis(psi0, 0.21, 0.03, 2 - axis)
+            assert rel_max(psi.cpu().numpy(), ref) < tol, (v, axis)
+            c = plan.fft3(_to_dev(psi0, prec), -1)
+            assert rel_max(c.cpu().numpy(), fft3(psi0)) < tol * 4, (v, axis)
+            e = plan.energies(_to_dev(psi0, prec))
+            base = psi0.astype(np.complex64).astype(np.complex128) if prec == "c64" else psi0
+            d = O.diagnostics(base, 0.21, 1.7)
+            for k in ("mass", "energy", "e_kin", "e_kin_i", "e_q"):
+                assert abs(e[k] - d[k]) <= (1e-10 if prec == "c128" else 3e-5) * max(abs(d[k]), 1e-3), (v, axis, k)
+            plan.close()
+
+
+def test_autotune_and_cache(tmp_path):
+    import json
+    import paper_2003_03590_amd as gp
+    cache = str(tmp_path / "tune.json")
+    plan = _plan(64, 0.3, 4.0, 0.01, "c64")
+    chosen = plan.autotune(reps=2, cache=cache)
+    data = json.load(open(cache))
+    assert len(data) == 3 and all(k.split("/")[1] == "c64" for k in data)
+    plan2 = _plan(64, 0.3, 4.0, 0.01, "c64")
+    assert plan2.autotune(reps=2, cache=cache) == chosen
+    psi0 = I.random_field(64, seed=77)
+    psi = _to_dev(psi0, "c64")
+    plan2.step_n(psi, 2)
+    ref = O.evolve(psi0.astype(np.complex64).astype(np.complex128), 0.3, 4.0, 0.01, 2)
+    assert rel_l2(psi.cpu().numpy(), ref) < 2e-6
+    # a batch plan re-records its graph after tuning
+    bp = gp.BatchPlan([dict(n=64, alpha=0.3, beta=4.0, dt=0.01), dict(n=96, alpha=0.2, beta=5.0, dt=0.01)], "c64")
+    sts = [_to_dev(I.random_field(64, seed=1), "c64"), _to_dev(I.random_field(96, seed=2), "c64")]
+    bp.step_n(sts, 1)
+    bp.autotune(reps=2, cache=cache)
+    bp.step_n(sts, 1)
+    assert len(json.load(open(cache))) >= 6
