@@ -39,10 +39,12 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
-def run_form(gp, torch, psi0_np, w, prec, steps, warmup, timed=True):
+def run_form(gp, torch, psi0_np, w, prec, steps, warmup, tune=True):
     """Time `steps` bench steps (100 split steps + diagnostics each) after `warmup`."""
     n = w["n"]
     plan = gp.Plan(n, w["alpha"], w["beta"], w["dt"], prec)
+    if tune:
+        plan.autotune(reps=5)
     dt = torch.complex128 if prec == "c128" else torch.complex64
     psi = torch.from_numpy(psi0_np).to("cuda").to(dt).contiguous()
     stream = torch.cuda.current_stream()
@@ -74,6 +76,38 @@ def run_form(gp, torch, psi0_np, w, prec, steps, warmup, timed=True):
     out = psi.to(torch.complex128).cpu().numpy()
     return dict(plan=plan, wall=wall, step_ms=step_ms, mean_pass_ms=mean_pass_ms, dE=dE, dN=dN, psi=out,
                 energies=energies, spec=spec)
+
+
+def ensemble_form(gp, torch, I):
+    """The 48-run ensemble (32 at 64^3, 16 at 96^3, complex64, dt = 1e-3, 300 steps)
+    advanced by one HIP-graph launch after autotuning; grid-point.steps/s summed
+    over runs and the per-run drift of mass and energy."""
+    import numpy as np
+    w = I.WORKLOADS["ens48"]
+    runs = [dict(r, dt=w["dt"]) for r in w["runs"]]
+    bp = gp.BatchPlan(runs, "c64")
+    bp.autotune(reps=3)
+    init = [torch.from_numpy(np.exp(1j * I.srp_fourier_theta(r["n"], w["K"], r["seed"]))).to("cuda")
+            .to(torch.complex64).contiguous() for r in runs]
+    states = [x.clone() for x in init]
+    bp.step_n(states, w["steps"])           # records and runs the graph once
+    torch.cuda.synchronize()
+    for s, x in zip(states, init):
+        s.copy_(x)
+    e0 = bp.energies(states)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    bp.step_n(states, w["steps"])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    e1 = bp.energies(states)
+    pts = sum(float(r["n"]) ** 3 for r in runs)
+    return {"value": pts * w["steps"] / el, "unit": "grid-point.steps/s (summed over runs)",
+            "runs": len(runs), "steps": w["steps"], "seconds": el,
+            "hbm_GBs": 6.0 * pts * 8 * (w["steps"] + 1) / el / 1e9,
+            "max_dN": float(np.max(np.abs(e1[:, 0] - e0[:, 0]) / e0[:, 0])),
+            "max_dE": float(np.max(np.abs(e1[:, 1] - e0[:, 1]) / e0[:, 1])),
+            "launch": "one HIP graph (grouped launches per size and axis)"}
 
 
 def passes_mode(gp, torch, spec, reps):
@@ -135,6 +169,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--passes", default=None, metavar="N:PREC",
                     help="profiling mode: time each axis pass alone on an N^3 field (PREC c128|c64) "
                          "and one device copy of the same bytes, then exit")
@@ -160,7 +196,7 @@ def main(argv=None):
     psi0 = I.tg_psi(n, xi, expo)
     npts = float(n) ** 3
 
-    f64 = run_form(gp, torch, psi0, w, "c128", a.steps, a.warmup)
+    f64 = run_form(gp, torch, psi0, w, "c128", a.steps, a.warmup, tune=not a.no_tune)
     split_steps = a.steps * DIAG_EVERY
     value = npts * split_steps / f64["wall"]
     step_only = npts * split_steps / (sum(f64["step_ms"]) / 1e3)
@@ -196,7 +232,7 @@ def main(argv=None):
         "schedule": [f64["plan"].schedule(ax) for ax in range(3)],
     }
     if not a.no_fp32:
-        f32 = run_form(gp, torch, psi0, w, "c64", a.steps, a.warmup)
+        f32 = run_form(gp, torch, psi0, w, "c64", a.steps, a.warmup, tune=not a.no_tune)
         v32 = npts * split_steps / f32["wall"]
         rel = float(np.linalg.norm(f32["psi"] - f64["psi"]) / np.linalg.norm(f64["psi"]))
         ach32 = 2.0 * npts * 8 / (f32["mean_pass_ms"] / 1e3) / 1e9
@@ -204,7 +240,10 @@ def main(argv=None):
                        "value_step_only": npts * split_steps / (sum(f32["step_ms"]) / 1e3),
                        "dE": f32["dE"], "dN": f32["dN"], "rel_l2_psi_vs_f64_gpu": rel,
                        "axis_pass_gbs": ach32, "axis_pass_frac": ach32 / HBM_PEAK_GBS,
-                       "mean_launch_us": f32["mean_pass_ms"] * 1e3}
+                       "mean_launch_us": f32["mean_pass_ms"] * 1e3,
+                       "schedule": [f32["plan"].schedule(ax) for ax in range(3)]}
+    if not a.no_ensemble:
+        res["ensemble"] = ensemble_form(gp, torch, I)
     if not a.no_cpu_baseline:
         res["cpu_baseline"] = oracle_sample(psi0, w)
     print(json.dumps(res))

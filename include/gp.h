@@ -107,6 +107,14 @@ GP_API int32_t gp_nshell(const gp_plan_t* p);
  * construction, eq. SRP_Init).  theta: dev, N^3 doubles; psi: dev, out. */
 GP_API gp_status gp_init_phase(gp_plan_t* p, const double* theta, void* psi);
 
+/* Random-vortex-ring initial condition (RVR section): psi = product over npairs
+ * ring pairs, each the pair ansatz psi_VR(z - d/2) conj(psi_VR(z + d/2)) (Pade core
+ * profile of width xi, phase atan2(z~, r - R)) times the conjugates of its six mirror
+ * images, evaluated at ((x, y, z) permuted) - (X, Y, Z) mod 2 pi.  pairs: host,
+ * npairs x 6 doubles (R, d, X, Y, Z, permutation 0..5 in the order (x,y,z), (x,z,y),
+ * (y,x,z), (y,z,x), (z,x,y), (z,y,x)).  psi: dev, out.  Synchronizes. */
+GP_API gp_status gp_init_rvr(gp_plan_t* p, const double* pairs, int32_t npairs, double xi, void* psi);
+
 /* One directional linear sub-step S(s, L_axis) psi = F_j^-1 exp(-i alpha k_j^2 s) F_j psi,
  * in place (time-evolution section).  axis: 0 = x, 1 = y, 2 = z. */
 GP_API gp_status gp_substep_linear(gp_plan_t* p, void* psi, int32_t axis, double s);

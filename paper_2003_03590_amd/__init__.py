@@ -128,6 +128,14 @@ class Plan:
         _check(lib().gp_init_phase(self._h, C.c_void_p(_ptr(theta)), self._field(psi)))
         return psi
 
+    def init_rvr(self, pairs, xi: float, out=None):
+        """Random vortex-ring pairs: ``pairs`` is a sequence of (R, d, X, Y, Z, perm)."""
+        arr = np.ascontiguousarray(np.asarray(pairs, dtype=np.float64).reshape(-1, 6))
+        psi = self.empty() if out is None else out
+        _check(lib().gp_init_rvr(self._h, arr.ctypes.data_as(C.POINTER(C.c_double)), int(arr.shape[0]),
+                                 float(xi), self._field(psi)))
+        return psi
+
     def step_n(self, psi, nsteps: int):
         _check(lib().gp_step_n(self._h, self._field(psi), int(nsteps)))
         return psi

@@ -43,6 +43,7 @@ SIGNATURES = {
     "gp_work_bytes": (C.c_size_t, [P]),
     "gp_nshell": (C.c_int32, [P]),
     "gp_init_phase": (ST, [P, P, P]),
+    "gp_init_rvr": (ST, [P, C.POINTER(C.c_double), C.c_int32, C.c_double, P]),
     "gp_substep_linear": (ST, [P, P, C.c_int32, C.c_double]),
     "gp_substep_nonlinear": (ST, [P, P, C.c_double]),
     "gp_step_n": (ST, [P, P, C.c_int64]),

@@ -155,6 +155,12 @@ __device__ __forceinline__ void exchange(cplx<Real>* lds, cplx<Real>* v, int t, 
   get<Real, S, KIND, TO>(lds, v, t, col);
 }
 
+// table entry i addressed as a 32-bit byte offset from the (uniform) table base
+template <class Real>
+__device__ __forceinline__ Tab<Real> tab_at(const Tab<Real>* __restrict__ t, int i) {
+  return *reinterpret_cast<const Tab<Real>*>(reinterpret_cast<const char*>(t) + (unsigned)i * (unsigned)sizeof(Tab<Real>));
+}
+
 // forward DIF stage s: butterfly over digit s, then twiddle W_{L_s}^{lo*k}
 template <class Real, class S, int s>
 __device__ __forceinline__ void fwd_stage(cplx<Real>* v, int t, const Tab<Real>* __restrict__ tw) {
@@ -168,7 +174,7 @@ __device__ __forceinline__ void fwd_stage(cplx<Real>* v, int t, const Tab<Real>*
     if constexpr (Ms > 1) {
       const int lo = (t + S::T * j) % Ms;
 #pragma unroll
-      for (int k = 1; k < R; ++k) x[k] = tmul(x[k], tw[lo * k * STEP]);
+      for (int k = 1; k < R; ++k) x[k] = tmul(x[k], tab_at(tw, lo * k * STEP));
     }
 #pragma unroll
     for (int k = 0; k < R; ++k) v[j + B * k] = x[k];
@@ -187,7 +193,7 @@ __device__ __forceinline__ void inv_stage(cplx<Real>* v, int t, const Tab<Real>*
     if constexpr (Ms > 1) {
       const int lo = (t + S::T * j) % Ms;
 #pragma unroll
-      for (int k = 1; k < R; ++k) x[k] = tmulc(x[k], tw[lo * k * STEP]);
+      for (int k = 1; k < R; ++k) x[k] = tmulc(x[k], tab_at(tw, lo * k * STEP));
     }
     Dft<R, +1, Real>::run(x);
 #pragma unroll
@@ -270,16 +276,24 @@ __global__ __launch_bounds__(S::THREADS) void axis_pass(PassArgs a) {
   const long p = (long)tile * W + col;
   const bool active = p < a.npencils;
   const long pp = active ? p : 0;
-  const long base = (pp / a.inner) * a.outer + (pp % a.inner);
   const long es = a.es;
-  const C* __restrict__ in = reinterpret_cast<const C*>(a.in);
-  C* __restrict__ out = reinterpret_cast<C*>(a.out);
+  // Addressing: element e of this lane sits at
+  //   bbase + e*T*es   (uniform: first pencil of the tile, scalar registers)
+  // + loff             (per lane, < 2^32 bytes for every supported shape)
+  // so each access is a scalar-base + 32-bit-offset load or store.
+  const long p0 = (long)tile * W;
+  const long bbase = (p0 / a.inner) * a.outer + (p0 % a.inner);
+  const unsigned loff =
+      (unsigned)(((pp / a.inner) * a.outer + (pp % a.inner) - bbase + (long)t * es) * (long)sizeof(C));
+  const long estep = (long)T * es * (long)sizeof(C);
+  const char* __restrict__ inb = reinterpret_cast<const char*>(a.in) + bbase * (long)sizeof(C);
+  char* __restrict__ outb = reinterpret_cast<char*>(a.out) + bbase * (long)sizeof(C);
   const Tab<Real>* __restrict__ tw = reinterpret_cast<const Tab<Real>*>(a.tw);
 
   C v[E];
   if (active) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = in[base + (long)(t + T * e) * es];
+    for (int e = 0; e < E; ++e) v[e] = *reinterpret_cast<const C*>(inb + e * estep + loff);
   } else {
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = mk(Real(0), Real(0));
@@ -290,11 +304,11 @@ __global__ __launch_bounds__(S::THREADS) void axis_pass(PassArgs a) {
 #pragma unroll
       for (int e = 0; e < E; ++e) v[e] = nl_rotate(v[e], a.nl_coef);
     } else if constexpr (PRO == PRO_ADJ_NL) {
-      const C* __restrict__ phi = reinterpret_cast<const C*>(a.aux);
+      const char* __restrict__ phib = reinterpret_cast<const char*>(a.aux) + bbase * (long)sizeof(C);
       const Real coef = Real(a.nl_coef);
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        const C f = active ? phi[base + (long)(t + T * e) * es] : mk(Real(0), Real(0));
+        const C f = active ? *reinterpret_cast<const C*>(phib + e * estep + loff) : mk(Real(0), Real(0));
         v[e] = nl_adjoint(v[e], f, coef);
       }
     } else if constexpr (PRO == PRO_DENSITY) {
@@ -322,7 +336,8 @@ __global__ __launch_bounds__(S::THREADS) void axis_pass(PassArgs a) {
           for (int j = 0; j < B; ++j) {
             const int pos = stage_pos<S, L>(t, j, r);
             const C x = v[j + B * r];
-            acc += a.ksq[pos] * ((double)x.x * x.x + (double)x.y * x.y);
+            acc += *reinterpret_cast<const double*>(reinterpret_cast<const char*>(a.ksq) + (unsigned)pos * 8u) *
+                   ((double)x.x * x.x + (double)x.y * x.y);
           }
         if (!active) acc = 0.0;
         // fixed-order reduction: wave butterfly, then waves in order
@@ -342,7 +357,7 @@ __global__ __launch_bounds__(S::THREADS) void axis_pass(PassArgs a) {
 #pragma unroll
         for (int j = 0; j < B; ++j) {
           const int pos = stage_pos<S, L>(t, j, r);
-          v[j + B * r] = tmul(v[j + B * r], mult[pos]);
+          v[j + B * r] = tmul(v[j + B * r], tab_at(mult, pos));
         }
       inverse_all<Real, S, KIND, L>(v, lds, t, col, tw);
     } else {  // FWD: reorder to natural frequency order
@@ -355,7 +370,7 @@ __global__ __launch_bounds__(S::THREADS) void axis_pass(PassArgs a) {
 
   if (active) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) out[base + (long)(t + T * e) * es] = v[e];
+    for (int e = 0; e < E; ++e) *reinterpret_cast<C*>(outb + e * estep + loff) = v[e];
   }
 }
 

@@ -28,6 +28,9 @@ void launch_loss_lambda2(int prec, void* lam, const void* e0, const void* e1, co
 void launch_phase_grad(int prec, const void* psi0, const void* lam0, double* out, long n, hipStream_t st);
 void launch_axis_power(int prec, const void* F, long n, long div, int nj, unsigned blocks, long chunk,
                        double* part, hipStream_t st);
+void launch_init_rvr(int prec, const void* pairs, int npairs, double xi, double a1, double a2, double b1, int nx,
+                     int ny, int nz, void* psi, hipStream_t st);
+size_t ringpar_bytes();
 void launch_structure_final(const double* pk, int nj, double ntot, double* out, hipStream_t st);
 
 }  // namespace gpk

@@ -470,4 +470,90 @@ void launch_structure_final(const double* pk, int nj, double ntot, double* out, 
   hipLaunchKernelGGL(k_structure_final, dim3(1), dim3(256), 0, st, pk, nj, ntot, out);
 }
 
+// ----------------------------------------------------------------- random vortex rings
+// Initial condition of the random-vortex-ring construction (RVR section): product over
+// pairs of the periodised ring-pair ansatz, evaluated at translated, axis-permuted
+// coordinates.
+struct RingPar { double R, d, X, Y, Z; int perm; };
+
+__device__ __forceinline__ void ring_eval(double x, double y, double z, double R, double xi, double pa1, double pa2,
+                                          double pb1, double* re, double* im) {
+  const double pi = 3.141592653589793238462643383279502884;
+  const double xt = x - pi, yt = y - pi, zt = z - pi;
+  const double dr = sqrt(xt * xt + yt * yt) - R;
+  const double dist = sqrt(dr * dr + zt * zt);
+  if (dist == 0.0) { *re = 0.0; *im = 0.0; return; }
+  const double e2 = (dist / xi) * (dist / xi), e4 = e2 * e2;
+  const double f = sqrt((pa1 * e2 + pa2 * e4) / (1.0 + pb1 * e2 + pa2 * e4));
+  // f exp(i atan2(zt, dr)) = f (dr + i zt) / dist
+  *re = f * dr / dist;
+  *im = f * zt / dist;
+}
+
+// pair ring(z - d/2) * conj(ring(z + d/2))
+__device__ __forceinline__ void pair_eval(double x, double y, double z, double R, double d, double xi, double a1,
+                                          double a2, double b1, double* re, double* im) {
+  double ar, ai, br, bi;
+  ring_eval(x, y, z - 0.5 * d, R, xi, a1, a2, b1, &ar, &ai);
+  ring_eval(x, y, z + 0.5 * d, R, xi, a1, a2, b1, &br, &bi);
+  *re = ar * br + ai * bi;
+  *im = ai * br - ar * bi;
+}
+
+template <class Real>
+__global__ __launch_bounds__(256) void k_init_rvr(const RingPar* __restrict__ pairs, int npairs, double xi, double a1,
+                                                  double a2, double b1, int nx, int ny, int nz, void* psi) {
+  const double two_pi = 6.283185307179586476925286766559;
+  const long n = (long)nx * ny * nz;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const int ix = (int)(i % nx), iy = (int)((i / nx) % ny), iz = (int)(i / ((long)nx * ny));
+    const double c[3] = {two_pi * ix / nx, two_pi * iy / ny, two_pi * iz / nz};
+    double pr = 1.0, pim = 0.0;
+    for (int q = 0; q < npairs; ++q) {
+      const RingPar P = pairs[q];
+      // permuted coordinates (x, y, z) -> (c[o0], c[o1], c[o2])
+      int o0, o1, o2;
+      switch (P.perm) {
+        case 0: o0 = 0; o1 = 1; o2 = 2; break;
+        case 1: o0 = 0; o1 = 2; o2 = 1; break;
+        case 2: o0 = 1; o1 = 0; o2 = 2; break;
+        case 3: o0 = 1; o1 = 2; o2 = 0; break;
+        case 4: o0 = 2; o1 = 0; o2 = 1; break;
+        default: o0 = 2; o1 = 1; o2 = 0; break;
+      }
+      double sx = fmod(c[o0] - P.X, two_pi), sy = fmod(c[o1] - P.Y, two_pi), sz = fmod(c[o2] - P.Z, two_pi);
+      if (sx < 0) sx += two_pi;
+      if (sy < 0) sy += two_pi;
+      if (sz < 0) sz += two_pi;
+      // periodised pair: the pair times the conjugates of its six mirror images
+      double tr, ti;
+      pair_eval(sx, sy, sz, P.R, P.d, xi, a1, a2, b1, &tr, &ti);
+      const double L2 = 2.0 * two_pi;
+      const double img[6][3] = {{L2 - sx, sy, sz}, {-sx, sy, sz}, {sx, L2 - sy, sz},
+                                {sx, -sy, sz},     {sx, sy, L2 - sz}, {sx, sy, -sz}};
+#pragma unroll
+      for (int m = 0; m < 6; ++m) {
+        double ur, ui;
+        pair_eval(img[m][0], img[m][1], img[m][2], P.R, P.d, xi, a1, a2, b1, &ur, &ui);
+        const double nr = tr * ur + ti * ui, ni = ti * ur - tr * ui;     // t * conj(u)
+        tr = nr; ti = ni;
+      }
+      const double nr = pr * tr - pim * ti, ni = pr * ti + pim * tr;
+      pr = nr; pim = ni;
+    }
+    stc<Real>(psi, i, pr, pim);
+  }
+}
+
+void launch_init_rvr(int prec, const void* pairs, int npairs, double xi, double a1, double a2, double b1, int nx,
+                     int ny, int nz, void* psi, hipStream_t st) {
+  const long n = (long)nx * ny * nz;
+  const RingPar* pp = reinterpret_cast<const RingPar*>(pairs);
+  if (prec == P_C128)
+    hipLaunchKernelGGL(k_init_rvr<double>, dim3(grid_for(n, 256, 1u << 20)), dim3(256), 0, st, pp, npairs, xi, a1, a2, b1, nx, ny, nz, psi);
+  else
+    hipLaunchKernelGGL(k_init_rvr<float>, dim3(grid_for(n, 256, 1u << 20)), dim3(256), 0, st, pp, npairs, xi, a1, a2, b1, nx, ny, nz, psi);
+}
+size_t ringpar_bytes() { return sizeof(RingPar); }
+
 }  // namespace gpk

@@ -587,6 +587,36 @@ gp_status gp_init_phase(gp_plan_t* p, const double* theta, void* psi) {
   return check_launch(p);
 }
 
+gp_status gp_init_rvr(gp_plan_t* p, const double* pairs, int32_t npairs, double xi, void* psi) {
+  gp_status st = usable(p);
+  if (st != GP_OK) return st;
+  if (!pairs || !psi || npairs < 0) return fail(GP_ERR_ARG, "null argument or negative pair count");
+  if (!(xi > 0.0) || !std::isfinite(xi)) return fail(GP_ERR_ARG, "core width xi must be positive");
+  // host pair table -> device, in the layout of the kernel's ring parameters
+  struct RP { double R, d, X, Y, Z; int perm; };
+  if (ringpar_bytes() != sizeof(RP)) return fail(GP_ERR_STATE, "ring parameter layout mismatch");
+  std::vector<RP> h(std::max(1, npairs));
+  for (int q = 0; q < npairs; ++q) {
+    const double* v = pairs + 6 * q;
+    const int perm = (int)v[5];
+    if (perm < 0 || perm > 5 || !(v[0] > 0.0)) return fail(GP_ERR_ARG, "pair %d: radius must be > 0, perm in 0..5", q);
+    h[q] = RP{v[0], v[1], v[2], v[3], v[4], perm};
+  }
+  void* d = nullptr;
+  HIPCHK(p, hipMalloc(&d, h.size() * sizeof(RP)));
+  hipError_t e = hipMemcpyAsync(d, h.data(), h.size() * sizeof(RP), hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) {
+    const double s201 = std::sqrt(201.0);
+    launch_init_rvr(p->prec, d, npairs, xi, (73.0 + 3.0 * s201) / 352.0, (6.0 + s201) / 528.0, (21.0 + s201) / 96.0,
+                    p->d.n[0], p->d.n[1], p->d.n[2], psi, p->stream);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  (void)hipFree(d);
+  if (e != hipSuccess) { p->broken = true; return fail(GP_ERR_HIP, "gp_init_rvr: %s", hipGetErrorString(e)); }
+  return GP_OK;
+}
+
 gp_status gp_substep_linear(gp_plan_t* p, void* psi, int32_t axis, double s) {
   gp_status st = usable(p);
   if (st != GP_OK) return st;
