@@ -29,6 +29,24 @@ WORKLOAD = "tg256"
 DIAG_EVERY = 100
 
 
+def pass_traffic():
+    """HBM bytes per axis-pass launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size), or None when
+    the kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "axis_pass_tg256_traffic.json")
+    try:
+        rec = json.load(open(path))
+        h = hashlib.sha256()
+        for f in rec["source_files"]:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest() != rec["source_sha256"]:
+            return None
+        return rec["traffic_bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -225,7 +243,7 @@ def main(argv=None):
         "hbm_gbs_per_split_step": 6.0 * npts * S / (sum(f64["step_ms"]) / 1e3 / split_steps) / 1e9,
         "bytes_per_split_step_min": 6.0 * npts * S,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": pass_traffic(),
                      "kernel": "axis_pass (x: fused nonlinear + propagator, y, z: propagator), mean of the three",
                      "per_launch_bytes": bytes_per_pass, "mean_launch_us": f64["mean_pass_ms"] * 1e3},
         "drift_f64": {"dE": f64["dE"], "dN": f64["dN"]},
