@@ -376,6 +376,7 @@ int first_real_axis(const gp_plan_s* p) {
 }
 
 // L(tau) on psi in place, the nonlinear rotation of coefficient nl (if any) fused in front
+// of the first pass
 gp_status linear_all(gp_plan_s* p, void* psi, int tau, bool with_nl, double nl) {
   const int c = first_real_axis(p);
   gp_status st;
