@@ -13,9 +13,16 @@
 // Forward stages are decimation-in-frequency butterflies done in registers, with an
 // LDS exchange between stages; after the last stage position p holds the coefficient
 // of the digit-reversed frequency.  PROP multiplies there by a table already stored in
-// position order and runs the exact inverse (conjugate-twiddle DIT) stages in reverse, so
+// that order and runs the exact inverse (conjugate-twiddle DIT) stages in reverse, so
 // no reordering pass is ever needed.  W pencils share one workgroup; for the strided
 // axes (y, z) the W pencils are x-adjacent so each global access is a W*S-byte row.
+//
+// Table layouts (built on the host for the schedule in use): every table load of one
+// instruction reads consecutive entries across the lanes, so it costs a few vector-L1
+// requests instead of one per lane.
+//   multiplier / k^2: the entry of position g*R_last + r is stored at r*(N/R_last) + g
+//                     (g = t + T*j runs over the lanes of one load)
+//   twiddles        : stage s keeps W_{R_s M_s}^{lo k} at TWOFF(s) + (k-1)*M_s + lo
 #pragma once
 
 #include "gp_device.h"
@@ -41,7 +48,7 @@ struct PassArgs {
   const void* in;          // input field (complex, working precision)
   void* out;               // output field (may equal in)
   const void* mult;        // PROP: multiplier in position order (N_j Tab<Real> entries)
-  const void* tw;          // W_N^m = exp(-2 pi i m / N_j), m < N_j (Tab<Real> entries)
+  const void* tw;          // per-stage twiddles W_{R M}^{lo k} (Tab<Real> entries, layout above)
   const void* aux;         // PRO_ADJ_NL: forward state phi at the same points
   const double* ksq;       // k_j^2 in position order (kinetic accumulation)
   double* kin_partial;     // per-workgroup partial sum of k_j^2 |F_j v|^2 (or null)
@@ -61,6 +68,13 @@ struct Sched {
   static constexpr int M(int s) { int m = 1; for (int i = s + 1; i < NS; ++i) m *= rad(i); return m; }
   // product of the radices before stage s (the frequency weight of stage s)
   static constexpr int K(int s) { int k = 1; for (int i = 0; i < s; ++i) k *= rad(i); return k; }
+  // twiddle sub-table of stage s: entries W_{R M}^{lo k} at (k-1)*M(s) + lo, stages with
+  // M(s) > 1 stored one after another
+  static constexpr int TWOFF(int s) {
+    int o = 0;
+    for (int i = 0; i < s; ++i) if (M(i) > 1) o += (rad(i) - 1) * M(i);
+    return o;
+  }
   static constexpr bool valid() {
     if (T * E != N) return false;
     int p = 1;
@@ -164,7 +178,7 @@ __device__ __forceinline__ Tab<Real> tab_at(const Tab<Real>* __restrict__ t, int
 // forward DIF stage s: butterfly over digit s, then twiddle W_{L_s}^{lo*k}
 template <class Real, class S, int s>
 __device__ __forceinline__ void fwd_stage(cplx<Real>* v, int t, const Tab<Real>* __restrict__ tw) {
-  constexpr int R = S::rad(s), B = S::E / R, Ms = S::M(s), Ls = R * Ms, STEP = S::N / Ls;
+  constexpr int R = S::rad(s), B = S::E / R, Ms = S::M(s);
 #pragma unroll
   for (int j = 0; j < B; ++j) {
     cplx<Real> x[R];
@@ -174,7 +188,7 @@ __device__ __forceinline__ void fwd_stage(cplx<Real>* v, int t, const Tab<Real>*
     if constexpr (Ms > 1) {
       const int lo = (t + S::T * j) % Ms;
 #pragma unroll
-      for (int k = 1; k < R; ++k) x[k] = tmul(x[k], tab_at(tw, lo * k * STEP));
+      for (int k = 1; k < R; ++k) x[k] = tmul(x[k], tab_at(tw, S::TWOFF(s) + (k - 1) * Ms + lo));
     }
 #pragma unroll
     for (int k = 0; k < R; ++k) v[j + B * k] = x[k];
@@ -184,7 +198,7 @@ __device__ __forceinline__ void fwd_stage(cplx<Real>* v, int t, const Tab<Real>*
 // inverse of fwd_stage (up to the factor R): conjugate twiddle, then inverse butterfly
 template <class Real, class S, int s>
 __device__ __forceinline__ void inv_stage(cplx<Real>* v, int t, const Tab<Real>* __restrict__ tw) {
-  constexpr int R = S::rad(s), B = S::E / R, Ms = S::M(s), Ls = R * Ms, STEP = S::N / Ls;
+  constexpr int R = S::rad(s), B = S::E / R, Ms = S::M(s);
 #pragma unroll
   for (int j = 0; j < B; ++j) {
     cplx<Real> x[R];
@@ -193,7 +207,7 @@ __device__ __forceinline__ void inv_stage(cplx<Real>* v, int t, const Tab<Real>*
     if constexpr (Ms > 1) {
       const int lo = (t + S::T * j) % Ms;
 #pragma unroll
-      for (int k = 1; k < R; ++k) x[k] = tmulc(x[k], tab_at(tw, lo * k * STEP));
+      for (int k = 1; k < R; ++k) x[k] = tmulc(x[k], tab_at(tw, S::TWOFF(s) + (k - 1) * Ms + lo));
     }
     Dft<R, +1, Real>::run(x);
 #pragma unroll
@@ -334,9 +348,9 @@ __global__ __launch_bounds__(S::THREADS) void axis_pass(PassArgs a) {
         for (int r = 0; r < S::rad(L); ++r)
 #pragma unroll
           for (int j = 0; j < B; ++j) {
-            const int pos = stage_pos<S, L>(t, j, r);
+            const int li = r * (S::N / S::rad(L)) + t + T * j;
             const C x = v[j + B * r];
-            acc += *reinterpret_cast<const double*>(reinterpret_cast<const char*>(a.ksq) + (unsigned)pos * 8u) *
+            acc += *reinterpret_cast<const double*>(reinterpret_cast<const char*>(a.ksq) + (unsigned)li * 8u) *
                    ((double)x.x * x.x + (double)x.y * x.y);
           }
         if (!active) acc = 0.0;
@@ -356,8 +370,7 @@ __global__ __launch_bounds__(S::THREADS) void axis_pass(PassArgs a) {
       for (int r = 0; r < S::rad(L); ++r)
 #pragma unroll
         for (int j = 0; j < B; ++j) {
-          const int pos = stage_pos<S, L>(t, j, r);
-          v[j + B * r] = tmul(v[j + B * r], tab_at(mult, pos));
+          v[j + B * r] = tmul(v[j + B * r], tab_at(mult, r * (S::N / S::rad(L)) + t + T * j));
         }
       inverse_all<Real, S, KIND, L>(v, lds, t, col, tw);
     } else {  // FWD: reorder to natural frequency order

@@ -75,6 +75,37 @@ int freq_pos(const PassEntry& e, int k) {
   return p;
 }
 
+// table index of DIF output position pos: positions are g*R_last + r; the tables are
+// stored r-major so that the lanes of one load instruction read consecutive entries
+int lane_idx(const PassEntry& e, int pos) {
+  const int rl = e.radix[e.NS - 1];
+  return (pos % rl) * (e.n / rl) + pos / rl;
+}
+
+// index of natural frequency k in the multiplier tables of schedule e
+int tab_idx(const PassEntry& e, int k) { return lane_idx(e, freq_pos(e, k)); }
+
+// per-stage twiddles: stage s with M_s = R_{s+1}...R_{NS-1} > 1 stores
+// W_{R_s M_s}^{lo k} = exp(-2 pi i lo k / (R_s M_s)) at off_s + (k-1) M_s + lo
+std::vector<double> stage_twiddles(const PassEntry& e) {
+  std::vector<double> tw;
+  for (int s = 0; s < e.NS; ++s) {
+    int M = 1;
+    for (int i = s + 1; i < e.NS; ++i) M *= e.radix[i];
+    if (M == 1) continue;
+    const int R = e.radix[s], L = R * M;
+    for (int k = 1; k < R; ++k)
+      for (int lo = 0; lo < M; ++lo) {
+        double c, sn;
+        cis2pi(-(long)lo * k, L, &c, &sn);
+        tw.push_back(c);
+        tw.push_back(sn);
+      }
+  }
+  if (tw.empty()) tw = {1.0, 0.0};     // single-stage schedules read no twiddle
+  return tw;
+}
+
 const int kSupported[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024};
 
 const PassEntry* find_entry(int n, int prec, int variant) {
@@ -236,13 +267,9 @@ gp_status build_tables(gp_plan_s* p, int a) {
   const double alpha = p->d.alpha, dt = p->d.dt;
   const double taus[NTAU] = {0.5 * dt, dt, -0.5 * dt, -dt};
   std::vector<int> pos(n);
-  for (int k = 0; k < n; ++k) pos[k] = A.e ? freq_pos(*A.e, k) : k;
+  for (int k = 0; k < n; ++k) pos[k] = A.e ? tab_idx(*A.e, k) : k;
   gp_status st;
-  if (A.e) {
-    std::vector<double> tw(2 * n);
-    for (int m = 0; m < n; ++m) cis2pi(-m, n, &tw[2 * m], &tw[2 * m + 1]);   // exp(-2 pi i m/n)
-    if ((st = upload_cplx(p, &A.tw, tw)) != GP_OK) return st;
-  }
+  if (A.e && (st = upload_cplx(p, &A.tw, stage_twiddles(*A.e))) != GP_OK) return st;
   for (int t = 0; t < NTAU; ++t) {
     std::vector<double> mp(2 * n), mn(2 * n);
     for (int k = 0; k < n; ++k) {
@@ -568,8 +595,11 @@ gp_status gp_select_variant(gp_plan_t* p, int32_t axis, int32_t variant) {
   if (p->ax[axis].n == 1) return variant == 0 ? GP_OK : fail(GP_ERR_ARG, "axis of length 1 has one variant");
   const PassEntry* e = find_entry(p->ax[axis].n, p->prec, variant);
   if (!e) return fail(GP_ERR_ARG, "no variant %d for n = %d", variant, p->ax[axis].n);
-  // the radix order defines the position order of the tables: rebuild them
+  // the radix order defines the order of the tables: rebuild them, and drop the
+  // one-off sub-step tables built for the previous order
   HIPCHK(p, p->stream ? hipStreamSynchronize(p->stream) : hipDeviceSynchronize());
+  for (auto it = p->substep_tables.begin(); it != p->substep_tables.end();)
+    it = it->first.first == axis ? p->substep_tables.erase(it) : std::next(it);
   const long old_blocks = p->ax[axis].blocks;
   if ((st = setup_axis(p, axis, variant)) != GP_OK) return st;
   if ((st = build_tables(p, axis)) != GP_OK) return st;
@@ -633,7 +663,7 @@ gp_status gp_substep_linear(gp_plan_t* p, void* psi, int32_t axis, double s) {
   for (int k = 0; k < n; ++k) {
     const double kk = (double)kfreq(k, n);
     const double ph = p->d.alpha * kk * kk * s;
-    const int ps = freq_pos(*A.e, k);
+    const int ps = tab_idx(*A.e, k);
     m[2 * ps] = std::cos(ph) / n;
     m[2 * ps + 1] = -std::sin(ph) / n;
   }
