@@ -111,3 +111,53 @@ def test_rvr1024_workload_segment():
     assert np.all(np.isfinite(sf)) and np.all(sf >= 0) and sf[-1] > sf[0]
     print(f"rvr1024: E0 {e0['energy']:.8f} E1 {e1['energy']:.8f} dE {abs(e1['energy'] - e0['energy']) / e0['energy']:.2e}")
     plan.close()
+
+
+@pytest.fixture(scope="module")
+def tg256():
+    """256^3 Taylor-Green state and one literal Strang step of the oracle from it."""
+    w = I.WORKLOADS["tg256"]
+    psi0 = I.tg_psi(w["n"], w["ic"][1]["xi"], w["ic"][1]["exponent"])
+    return w, psi0, O.evolve(psi0, w["alpha"], w["beta"], w["dt"], 1)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_tg256_in_measured_configuration(tg256, prec):
+    """256^3 Taylor-Green workload (alpha = 0.06942, beta = 28.81, dt = 5e-4) with
+    the autotuned schedules of the throughput measurement: one Strang step over
+    the whole field against the oracle's literal step, sampled pencils of each
+    axis sub-step, and the spectra summing to the energies."""
+    w, psi0, ref1 = tg256
+    n = w["n"]
+    plan = _plan(n, w["alpha"], w["beta"], w["dt"], prec)
+    plan.autotune(reps=5)
+    dt = torch.complex128 if prec == "c128" else torch.complex64
+    start = psi0.astype(np.complex64).astype(np.complex128) if prec == "c64" else psi0
+    dev0 = torch.from_numpy(start).to(DEV).to(dt).contiguous()
+    psi = dev0.clone()
+    plan.step_n(psi, 1)
+    got = psi.cpu().numpy().astype(np.complex128)
+    rel = float(np.linalg.norm(got - ref1) / np.linalg.norm(ref1))
+    print(f"tg256 {prec} [{'; '.join(plan.schedule(a) for a in range(3))}]: one step rel-L2 {rel:.2e}")
+    assert rel < (1e-12 if prec == "c128" else 2e-6)
+    s = 0.5 * w["dt"]
+    tol = 1e-13 if prec == "c128" else 2e-6 * math.log2(n)
+    rng = np.random.default_rng(3)
+    for axis in range(3):
+        q = dev0.clone()
+        plan.substep_linear(q, axis, s)
+        for _ in range(6):
+            i, j = (int(v) for v in rng.integers(0, n, 2))
+            sl = [(i, j, slice(None)), (i, slice(None), j), (slice(None), i, j)][axis]
+            ref = O.linear_substep_axis(start[sl].reshape(1, 1, n), w["alpha"], s, 2)[0, 0]
+            assert np.abs(q[sl].cpu().numpy().astype(np.complex128) - ref).max() < tol * np.abs(ref).max()
+    spec, e = plan.spectra(psi)
+    rt = 1e-9 if prec == "c128" else 1e-6        # FP32 spectral fields for complex64
+    assert abs(spec[0].sum() - e["e_kin_i"]) < rt * e["e_kin"]
+    assert abs(spec[0].sum() + spec[1].sum() - e["e_kin"]) < rt * e["e_kin"]
+    assert abs(spec[2].sum() - e["e_q"]) < rt * e["e_q"]
+    assert abs(spec[3].sum() - e["e_int"]) < rt * e["e_int"]
+    # E_kin + E_q + E_int equals E only up to the spectral truncation of |psi| at the
+    # vortex cores (2.7e-5 relative for this state); exact for band-limited |psi|
+    assert abs(e["e_kin"] + e["e_q"] + e["e_int"] - e["energy"]) < 1e-4 * e["energy"]
+    plan.close()

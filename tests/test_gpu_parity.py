@@ -110,6 +110,34 @@ def test_config_srp32_full_run():
     assert rel_l2(psi.cpu().numpy(), ref) < 1e-12
 
 
+def test_config_srp32_fp32_run():
+    """The same 32^3 run in complex64 (FP32 transforms and propagators, FP64 tables
+    and reductions): psi after 200 steps within 1e-5 relative L2 of the FP64
+    oracle, every diagnostic within 1e-5 of the oracle's, mass and energy drift
+    stated."""
+    w = I.WORKLOADS["srp32"]
+    theta = I.srp_fourier_theta(32, 4, 0)
+    plan = _plan(32, w["alpha"], w["beta"], w["dt"], "c64")
+    psi = plan.init_phase(torch.from_numpy(theta).to(DEV))
+    ref = np.exp(1j * theta)
+    e0 = plan.energies(psi)
+    drift_n = drift_e = 0.0
+    for blk in range(w["steps"] // w["diag_every"]):
+        plan.step_n(psi, w["diag_every"])
+        ref = O.evolve(ref, w["alpha"], w["beta"], w["dt"], w["diag_every"])
+        spec, e = plan.spectra(psi)
+        d = O.diagnostics(ref, w["alpha"], w["beta"])
+        for k in ("mass", "energy", "e_kin", "e_kin_i", "e_kin_c", "e_q", "e_int"):
+            assert abs(e[k] - d[k]) <= 1e-5 * max(abs(d[k]), 1e-3), (blk, k, e[k], d[k])
+        assert np.abs(spec - d["spec"]).max() <= 1e-5 * np.abs(d["spec"]).max()
+        drift_n = max(drift_n, abs(e["mass"] - e0["mass"]) / e0["mass"])
+        drift_e = max(drift_e, abs(e["energy"] - e0["energy"]) / e0["energy"])
+    err = rel_l2(psi.cpu().numpy().astype(np.complex128), ref)
+    print(f"srp32 complex64: rel-L2 {err:.2e}, drift N {drift_n:.2e}, drift E {drift_e:.2e}")
+    assert err < 1e-5
+    assert drift_n < 1e-6 and drift_e < 1e-5
+
+
 @pytest.mark.parametrize("prec", ["c128", "c64"])
 @pytest.mark.parametrize("shape", [(16, 16, 16), (12, 24, 8), (64, 32, 16), (96, 8, 4)], ids=lambda s: "x".join(map(str, s)))
 def test_diagnostics(shape, prec):

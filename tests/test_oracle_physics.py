@@ -270,3 +270,21 @@ def test_table1_parameters():
 
 def test_gamma_d_quarter():
     assert [gp.gamma_d_quarter(gp.table1_params(n)["alpha"]) for n in (128, 256, 512, 1024)] == [3, 6, 12, 25]
+
+
+def test_chaotic_regime_parity_floor():
+    """The oracle run twice on the 32^3 smoothed-random-phase workload (alpha = beta
+    = 1, dt = 1e-3, 200 steps), once with the dense DFT and once with the
+    mixed-radix FFT: the two transforms differ only in rounding order, so their
+    distance is the floor any complex128 parity claim stands on.  It must stay
+    well under the 1e-12 relative tolerance of the GPU parity tests."""
+    w = I.WORKLOADS["srp32"]
+    psi0 = np.exp(1j * I.srp_fourier_theta(32, 4, 0))
+    floors = []
+    a = b = psi0
+    for _ in range(w["steps"] // 40):
+        a = gp.evolve(a, w["alpha"], w["beta"], w["dt"], 40, engine="dft")
+        b = gp.evolve(b, w["alpha"], w["beta"], w["dt"], 40, engine="fft")
+        floors.append(np.linalg.norm(a - b) / np.linalg.norm(b))
+    print("rel-L2 DFT vs FFT every 40 steps:", " ".join(f"{f:.1e}" for f in floors))
+    assert max(floors) < 1e-12 / 4
