@@ -29,6 +29,19 @@
 
 namespace gpk {
 
+// global-memory pointers: accesses through them are global (not flat) instructions,
+// which count on the vector-memory counter only (the qualifier is for the device
+// compilation pass; the host pass only checks the kernel bodies)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GPK_GLOBAL __attribute__((address_space(1)))
+#else
+#define GPK_GLOBAL
+#endif
+template <class X>
+__device__ __forceinline__ const GPK_GLOBAL X* gptr(const void* p) { return (const GPK_GLOBAL X*)p; }
+template <class X>
+__device__ __forceinline__ GPK_GLOBAL X* gptr_mut(void* p) { return (GPK_GLOBAL X*)p; }
+
 enum PassKind { CONTIG = 0, STRIDED = 1 };
 enum PassMode { PROP = 0, FWD = 1, INV = 2 };
 // pointwise work fused in front of the transform (PRO_KIN: none, but accumulate
@@ -169,15 +182,16 @@ __device__ __forceinline__ void exchange(cplx<Real>* lds, cplx<Real>* v, int t, 
   get<Real, S, KIND, TO>(lds, v, t, col);
 }
 
-// table entry i addressed as a 32-bit byte offset from the (uniform) table base
-template <class Real>
-__device__ __forceinline__ Tab<Real> tab_at(const Tab<Real>* __restrict__ t, int i) {
-  return *reinterpret_cast<const Tab<Real>*>(reinterpret_cast<const char*>(t) + (unsigned)i * (unsigned)sizeof(Tab<Real>));
+// table entry i (32-bit index from the uniform table base; P is a global-memory or
+// an LDS pointer)
+template <class P>
+__device__ __forceinline__ auto tab_at(P t, int i) {
+  return t[(unsigned)i];
 }
 
 // forward DIF stage s: butterfly over digit s, then twiddle W_{L_s}^{lo*k}
-template <class Real, class S, int s>
-__device__ __forceinline__ void fwd_stage(cplx<Real>* v, int t, const Tab<Real>* __restrict__ tw) {
+template <class Real, class S, int s, class P>
+__device__ __forceinline__ void fwd_stage(cplx<Real>* v, int t, P tw) {
   constexpr int R = S::rad(s), B = S::E / R, Ms = S::M(s);
 #pragma unroll
   for (int j = 0; j < B; ++j) {
@@ -196,8 +210,8 @@ __device__ __forceinline__ void fwd_stage(cplx<Real>* v, int t, const Tab<Real>*
 }
 
 // inverse of fwd_stage (up to the factor R): conjugate twiddle, then inverse butterfly
-template <class Real, class S, int s>
-__device__ __forceinline__ void inv_stage(cplx<Real>* v, int t, const Tab<Real>* __restrict__ tw) {
+template <class Real, class S, int s, class P>
+__device__ __forceinline__ void inv_stage(cplx<Real>* v, int t, P tw) {
   constexpr int R = S::rad(s), B = S::E / R, Ms = S::M(s);
 #pragma unroll
   for (int j = 0; j < B; ++j) {
@@ -215,23 +229,21 @@ __device__ __forceinline__ void inv_stage(cplx<Real>* v, int t, const Tab<Real>*
   }
 }
 
-template <class Real, class S, int KIND, int s>
-__device__ __forceinline__ void forward_all(cplx<Real>* v, cplx<Real>* lds, int t, int col,
-                                            const Tab<Real>* __restrict__ tw) {
-  fwd_stage<Real, S, s>(v, t, tw);
+template <class Real, class S, int KIND, int s, class P>
+__device__ __forceinline__ void forward_all(cplx<Real>* v, cplx<Real>* lds, int t, int col, P tw) {
+  fwd_stage<Real, S, s, P>(v, t, tw);
   if constexpr (s + 1 < S::NS) {
     exchange<Real, S, KIND, s, s + 1>(lds, v, t, col);
-    forward_all<Real, S, KIND, s + 1>(v, lds, t, col, tw);
+    forward_all<Real, S, KIND, s + 1, P>(v, lds, t, col, tw);
   }
 }
 
-template <class Real, class S, int KIND, int s>
-__device__ __forceinline__ void inverse_all(cplx<Real>* v, cplx<Real>* lds, int t, int col,
-                                            const Tab<Real>* __restrict__ tw) {
-  inv_stage<Real, S, s>(v, t, tw);
+template <class Real, class S, int KIND, int s, class P>
+__device__ __forceinline__ void inverse_all(cplx<Real>* v, cplx<Real>* lds, int t, int col, P tw) {
+  inv_stage<Real, S, s, P>(v, t, tw);
   if constexpr (s > 0) {
     exchange<Real, S, KIND, s, s - 1>(lds, v, t, col);
-    inverse_all<Real, S, KIND, s - 1>(v, lds, t, col, tw);
+    inverse_all<Real, S, KIND, s - 1, P>(v, lds, t, col, tw);
   }
 }
 
@@ -286,104 +298,120 @@ __global__ __launch_bounds__(S::THREADS) void axis_pass(PassArgs a) {
   // in the same L2.
   const unsigned G = gridDim.x, b = blockIdx.x;
   const unsigned nfull = G / 8, rem = G % 8, xcd = b % 8;
-  const unsigned tile = xcd * nfull + (xcd < rem ? xcd : rem) + b / 8;
-  const long p = (long)tile * W + col;
-  const bool active = p < a.npencils;
-  const long pp = active ? p : 0;
+  const long tile = (long)xcd * nfull + (xcd < rem ? xcd : rem) + b / 8;
   const long es = a.es;
-  // Addressing: element e of this lane sits at
+  const long estep = (long)T * es * (long)sizeof(C);
+  const auto tw = gptr<Tab<Real>>(a.tw);
+  const auto mult = gptr<Tab<Real>>(a.mult);
+
+  // Addressing: element e of this lane in tile tl sits at
   //   bbase + e*T*es   (uniform: first pencil of the tile, scalar registers)
   // + loff             (per lane, < 2^32 bytes for every supported shape)
   // so each access is a scalar-base + 32-bit-offset load or store.
-  const long p0 = (long)tile * W;
-  const long bbase = (p0 / a.inner) * a.outer + (p0 % a.inner);
-  const unsigned loff =
-      (unsigned)(((pp / a.inner) * a.outer + (pp % a.inner) - bbase + (long)t * es) * (long)sizeof(C));
-  const long estep = (long)T * es * (long)sizeof(C);
-  const char* __restrict__ inb = reinterpret_cast<const char*>(a.in) + bbase * (long)sizeof(C);
-  char* __restrict__ outb = reinterpret_cast<char*>(a.out) + bbase * (long)sizeof(C);
-  const Tab<Real>* __restrict__ tw = reinterpret_cast<const Tab<Real>*>(a.tw);
+  // A lane past the last pencil (ragged last tile) takes the last pencil: it loads,
+  // transforms and stores exactly what that pencil's own lanes do, so every load and
+  // store is issued unconditionally (no branch around memory instructions) and the
+  // duplicate stores write equal bytes.
+  struct Where { long bbase; unsigned loff; bool active; };
+  auto where = [&](long tl) {
+    Where w;
+    const long p = tl * W + col;
+    w.active = p < a.npencils;
+    const long pp = w.active ? p : a.npencils - 1;
+    // pencil indices are below 2^20 for every supported shape: 32-bit division
+    // (no 64-bit division subroutine with its branches)
+    const unsigned inner = (unsigned)a.inner, q0 = (unsigned)(tl * W), q = (unsigned)pp;
+    w.bbase = (long)(q0 / inner) * a.outer + (long)(q0 % inner);
+    w.loff = (unsigned)(((long)(q / inner) * a.outer + (long)(q % inner) - w.bbase + (long)t * es) * (long)sizeof(C));
+    return w;
+  };
+  auto load = [&](C* v, const Where& w) {
+    const auto inb = gptr<char>(a.in) + w.bbase * (long)sizeof(C);
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = *(const GPK_GLOBAL C*)(inb + e * estep + w.loff);
+  };
 
-  C v[E];
-  if (active) {
+  double kin_acc = 0.0;
+  // transform one tile held in v (prologue, transform, multiplier, inverse) and store it
+  auto process = [&](C* v, const Where& cur) {
+    if constexpr (MODE != INV) {
+      if constexpr (PRO == PRO_NL) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = *reinterpret_cast<const C*>(inb + e * estep + loff);
-  } else {
+        for (int e = 0; e < E; ++e) v[e] = nl_rotate(v[e], a.nl_coef);
+      } else if constexpr (PRO == PRO_ADJ_NL) {
+        const auto phib = gptr<char>(a.aux) + cur.bbase * (long)sizeof(C);
+        const Real coef = Real(a.nl_coef);
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = mk(Real(0), Real(0));
-  }
-
-  if constexpr (MODE != INV) {
-    if constexpr (PRO == PRO_NL) {
+        for (int e = 0; e < E; ++e) {
+          const C f = *(const GPK_GLOBAL C*)(phib + e * estep + cur.loff);
+          v[e] = nl_adjoint(v[e], f, coef);
+        }
+      } else if constexpr (PRO == PRO_DENSITY) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = nl_rotate(v[e], a.nl_coef);
-    } else if constexpr (PRO == PRO_ADJ_NL) {
-      const char* __restrict__ phib = reinterpret_cast<const char*>(a.aux) + bbase * (long)sizeof(C);
-      const Real coef = Real(a.nl_coef);
-#pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const C f = active ? *reinterpret_cast<const C*>(phib + e * estep + loff) : mk(Real(0), Real(0));
-        v[e] = nl_adjoint(v[e], f, coef);
+        for (int e = 0; e < E; ++e) v[e] = mk(cabs2(v[e]) - Real(1), Real(0));
       }
-    } else if constexpr (PRO == PRO_DENSITY) {
-#pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = mk(cabs2(v[e]) - Real(1), Real(0));
     }
-  }
 
-  if constexpr (MODE == INV) {
-    if constexpr (S::NS > 1) exchange<Real, S, KIND, -1, S::NS - 1>(lds, v, t, col);
-    inverse_all<Real, S, KIND, S::NS - 1>(v, lds, t, col, tw);
-    const Real sc = Real(a.scale);
-#pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = cscale(v[e], sc);
-  } else {
-    forward_all<Real, S, KIND, 0>(v, lds, t, col, tw);
-    constexpr int L = S::NS - 1;
-    constexpr int B = E / S::rad(L);
-    if constexpr (MODE == PROP) {
-      if constexpr (PRO == PRO_KIN) {
-        double acc = 0.0;
-#pragma unroll
-        for (int r = 0; r < S::rad(L); ++r)
-#pragma unroll
-          for (int j = 0; j < B; ++j) {
-            const int li = r * (S::N / S::rad(L)) + t + T * j;
-            const C x = v[j + B * r];
-            acc += *reinterpret_cast<const double*>(reinterpret_cast<const char*>(a.ksq) + (unsigned)li * 8u) *
-                   ((double)x.x * x.x + (double)x.y * x.y);
-          }
-        if (!active) acc = 0.0;
-        // fixed-order reduction: wave butterfly, then waves in order
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-        if ((tid & 63) == 0) red[tid >> 6] = acc;
-        __syncthreads();
-        if (tid == 0) {
-          double s = 0.0;
-          for (int w = 0; w < S::THREADS / 64 + (S::THREADS % 64 ? 1 : 0); ++w) s += red[w];
-          a.kin_partial[blockIdx.x] = s;
-        }
-      }
-      const Tab<Real>* __restrict__ mult = reinterpret_cast<const Tab<Real>*>(a.mult);
-#pragma unroll
-      for (int r = 0; r < S::rad(L); ++r)
-#pragma unroll
-        for (int j = 0; j < B; ++j) {
-          v[j + B * r] = tmul(v[j + B * r], tab_at(mult, r * (S::N / S::rad(L)) + t + T * j));
-        }
-      inverse_all<Real, S, KIND, L>(v, lds, t, col, tw);
-    } else {  // FWD: reorder to natural frequency order
-      if constexpr (S::NS > 1) exchange<Real, S, KIND, L, -1>(lds, v, t, col);
+    if constexpr (MODE == INV) {
+      if constexpr (S::NS > 1) exchange<Real, S, KIND, -1, S::NS - 1>(lds, v, t, col);
+      inverse_all<Real, S, KIND, S::NS - 1>(v, lds, t, col, tw);
       const Real sc = Real(a.scale);
 #pragma unroll
       for (int e = 0; e < E; ++e) v[e] = cscale(v[e], sc);
-    }
-  }
-
-  if (active) {
+    } else {
+      forward_all<Real, S, KIND, 0>(v, lds, t, col, tw);
+      constexpr int L = S::NS - 1;
+      constexpr int B = E / S::rad(L);
+      if constexpr (MODE == PROP) {
+        if constexpr (PRO == PRO_KIN) {
+          double acc = 0.0;
 #pragma unroll
-    for (int e = 0; e < E; ++e) *reinterpret_cast<C*>(outb + e * estep + loff) = v[e];
+          for (int r = 0; r < S::rad(L); ++r)
+#pragma unroll
+            for (int j = 0; j < B; ++j) {
+              const int li = r * (S::N / S::rad(L)) + t + T * j;
+              const C x = v[j + B * r];
+              acc += gptr<double>(a.ksq)[(unsigned)li] *
+                     ((double)x.x * x.x + (double)x.y * x.y);
+            }
+          if (cur.active) kin_acc += acc;
+        }
+#pragma unroll
+        for (int r = 0; r < S::rad(L); ++r)
+#pragma unroll
+          for (int j = 0; j < B; ++j)
+            v[j + B * r] = tmul(v[j + B * r], tab_at(mult, r * (S::N / S::rad(L)) + t + T * j));
+        inverse_all<Real, S, KIND, L>(v, lds, t, col, tw);
+      } else {  // FWD: reorder to natural frequency order
+        if constexpr (S::NS > 1) exchange<Real, S, KIND, L, -1>(lds, v, t, col);
+        const Real sc = Real(a.scale);
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = cscale(v[e], sc);
+      }
+    }
+
+    const auto outb = gptr_mut<char>(a.out) + cur.bbase * (long)sizeof(C);
+#pragma unroll
+    for (int e = 0; e < E; ++e) *(GPK_GLOBAL C*)(outb + e * estep + cur.loff) = v[e];
+  };
+
+  C v[E];
+  const Where w = where(tile);
+  load(v, w);
+  process(v, w);
+
+  if constexpr (PRO == PRO_KIN) {
+    // fixed-order reduction: wave butterfly, then waves in order (one partial per workgroup)
+    double acc = kin_acc;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0.0;
+      for (int w = 0; w < S::THREADS / 64 + (S::THREADS % 64 ? 1 : 0); ++w) s += red[w];
+      gptr_mut<double>(a.kin_partial)[blockIdx.x] = s;
+    }
   }
 }
 
