@@ -9,7 +9,9 @@ default 10 timed bench steps are the workload's 1000 time steps.
 
 Printed: one JSON line with the throughput in grid-point.steps/s, the roofline
 of the axis-pass kernel (HIP events over the timed region), the complex64 form
-at its measured energy drift, and the CPU oracle timed on a bounded sample.
+at its measured energy drift, the 48-run ensemble, the 1024^3 complex64 workload
+(the axis pass on a state far larger than the last-level cache), and the CPU
+oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -128,6 +130,43 @@ def ensemble_form(gp, torch, I):
             "launch": "one HIP graph (grouped launches per size and axis)"}
 
 
+def large_form(gp, torch, I, steps=5):
+    """The 1024^3 complex64 workload (40 random vortex-ring pairs, alpha = 0.02603,
+    beta = 76.83, dt = 2.5e-4) with autotuned schedules: `steps` Strang steps timed
+    with HIP events on the plan's stream.  An 8 GiB state is far beyond the 256 MB
+    last-level cache, so this is the HBM-bound form of the axis pass."""
+    w = I.WORKLOADS["rvr1024"]
+    n = w["n"]
+    ic = w["ic"][1]
+    plan = gp.Plan(n, w["alpha"], w["beta"], w["dt"], "c64")
+    plan.autotune(reps=3)
+    pairs = [(p["R"], p["d"], p["X"], p["Y"], p["Z"], p["perm"]) for p in I.rvr_draws(ic["n_pairs"], ic["seed"])]
+    psi = plan.init_rvr(pairs, ic["xi"])
+    plan.step_n(psi, 1)
+    st = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(st)
+    plan.step_n(psi, steps)
+    b.record(st)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    launches = 3 * (steps + 1)
+    per_launch = 2.0 * float(n) ** 3 * 8
+    gbs = per_launch * launches / (ms / 1e3) / 1e9
+    out = {"workload": "rvr1024: 1024^3 complex64, 40 random vortex-ring pairs (seed 1), dt = 2.5e-4",
+           "steps": steps, "ms_per_step": ms / steps,
+           "value": float(n) ** 3 * steps / (ms / 1e3), "unit": "grid-point.steps/s",
+           "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": gbs / HBM_PEAK_GBS, "per_launch_bytes": per_launch,
+                        "mean_launch_us": ms * 1e3 / launches},
+           "schedule": [plan.schedule(ax) for ax in range(3)]}
+    plan.close()
+    del psi
+    torch.cuda.empty_cache()
+    return out
+
+
 def passes_mode(gp, torch, spec, reps):
     """Each axis pass (propagator sub-step S(s, L_j)) `reps` times on a random
     N^3 field, then `reps` device copies of the same bytes (calibration of the
@@ -189,6 +228,7 @@ def main(argv=None):
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-large", action="store_true", help="skip the 1024^3 complex64 HBM-bound form")
     ap.add_argument("--passes", default=None, metavar="N:PREC",
                     help="profiling mode: time each axis pass alone on an N^3 field (PREC c128|c64) "
                          "and one device copy of the same bytes, then exit")
@@ -262,6 +302,8 @@ def main(argv=None):
                        "schedule": [f32["plan"].schedule(ax) for ax in range(3)]}
     if not a.no_ensemble:
         res["ensemble"] = ensemble_form(gp, torch, I)
+    if not a.no_large:
+        res["large_1024_c64"] = large_form(gp, torch, I)
     if not a.no_cpu_baseline:
         res["cpu_baseline"] = oracle_sample(psi0, w)
     print(json.dumps(res))
