@@ -31,12 +31,12 @@ WORKLOAD = "tg256"
 DIAG_EVERY = 100
 
 
-def pass_traffic():
-    """HBM bytes per axis-pass launch from the committed rocprofv3 counter summary
+def pass_traffic(name="axis_pass_tg256_traffic.json"):
+    """HBM bytes per axis-pass launch from a committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size), or None when
     the kernel sources changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "axis_pass_tg256_traffic.json")
+    path = os.path.join(ROOT, "profiles", name)
     try:
         rec = json.load(open(path))
         h = hashlib.sha256()
@@ -159,6 +159,7 @@ def large_form(gp, torch, I, steps=5):
            "value": float(n) ** 3 * steps / (ms / 1e3), "unit": "grid-point.steps/s",
            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": gbs / HBM_PEAK_GBS, "per_launch_bytes": per_launch,
+                        "traffic": pass_traffic("axis_pass_rvr1024_traffic.json"),
                         "mean_launch_us": ms * 1e3 / launches},
            "schedule": [plan.schedule(ax) for ax in range(3)]}
     plan.close()
@@ -167,13 +168,20 @@ def large_form(gp, torch, I, steps=5):
     return out
 
 
-def passes_mode(gp, torch, spec, reps):
+def passes_mode(gp, torch, spec, reps, tune=False, variants=None):
     """Each axis pass (propagator sub-step S(s, L_j)) `reps` times on a random
     N^3 field, then `reps` device copies of the same bytes (calibration of the
-    FETCH_SIZE / WRITE_SIZE counters); prints one JSON line of event timings."""
+    FETCH_SIZE / WRITE_SIZE counters); prints one JSON line of event timings.
+    With `tune`, the schedules are autotuned first; `variants` (one schedule
+    variant per axis) fixes them instead, e.g. to those a timed run selected."""
     n, prec = spec.split(":")
     n = int(n)
     plan = gp.Plan(n, 0.05, 40.0, 1e-3, prec)
+    if tune:
+        plan.autotune(reps=3)
+    if variants:
+        for ax, v in enumerate(int(x) for x in variants.split(",")):
+            plan.select_variant(ax, v)
     dt = torch.complex128 if prec == "c128" else torch.complex64
     S = 16 if prec == "c128" else 8
     psi = torch.randn(n, n, n, dtype=dt, device="cuda")
@@ -233,6 +241,9 @@ def main(argv=None):
                     help="profiling mode: time each axis pass alone on an N^3 field (PREC c128|c64) "
                          "and one device copy of the same bytes, then exit")
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--tune", action="store_true", help="with --passes: autotune the schedules first")
+    ap.add_argument("--variants", default=None, metavar="VX,VY,VZ",
+                    help="with --passes: schedule variant of each axis (as reported by a timed run)")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU "
@@ -246,7 +257,7 @@ def main(argv=None):
     import paper_2003_03590_amd as gp
 
     if a.passes:
-        return passes_mode(gp, torch, a.passes, a.reps)
+        return passes_mode(gp, torch, a.passes, a.reps, tune=a.tune, variants=a.variants)
 
     w = I.WORKLOADS[WORKLOAD]
     n = w["n"]
