@@ -247,6 +247,32 @@ def test_batch_matches_single_runs():
         assert abs(e[i, 1] - O.energy(ref, r["alpha"], r["beta"])) < 1e-10 * abs(e[i, 1])
 
 
+def test_batch_graph_replays_with_eager_work_between():
+    """The ensemble step is recorded once as a HIP graph and replayed; four
+    replays with other GPU work (another plan's steps, the batch diagnostics,
+    torch kernels) and synchronizations between them, every replay checked
+    against the oracle advanced by the same number of steps."""
+    import paper_2003_03590_amd as gp
+    runs = [dict(n=16, alpha=0.4, beta=2.0, dt=0.01), dict(n=24, alpha=0.3, beta=3.0, dt=0.01),
+            dict(n=16, alpha=0.5, beta=1.0, dt=0.02)]
+    bp = gp.BatchPlan(runs, "c128")
+    refs = [I.random_field(r["n"], seed=70 + i) for i, r in enumerate(runs)]
+    states = [_to_dev(a, "c128") for a in refs]
+    other = _plan(12, 0.3, 2.0, 0.01)
+    x = _to_dev(I.random_field(12, seed=80), "c128")
+    for rep in range(4):
+        bp.step_n(states, 2)              # first call records the graph, later calls replay it
+        other.step_n(x, 1)
+        e = bp.energies(states)
+        y = (x * 2.0).abs().sum()
+        torch.cuda.synchronize()
+        assert math.isfinite(float(y))
+        for i, r in enumerate(runs):
+            refs[i] = O.evolve(refs[i], r["alpha"], r["beta"], r["dt"], 2)
+            assert rel_l2(states[i].cpu().numpy(), refs[i]) < 1e-12, (rep, i)
+            assert abs(e[i, 0] - O.mass(refs[i])) < 1e-12
+
+
 def test_errors_are_reported():
     import paper_2003_03590_amd as gp
     plan = _plan(8, 1.0, 1.0, 0.01)
