@@ -62,6 +62,18 @@ __device__ __forceinline__ cplx<float> tmulc(cplx<float> a, const Tab<float>& t)
   return mk(fmaf(a.x, t.hi.x, fmaf(a.y, t.hi.y, sr)), fmaf(a.y, t.hi.x, fmaf(-a.x, t.hi.y, si)));
 }
 
+// Multiplier between the forward and the inverse transform (propagator, spectral
+// derivative): an FP64 complex table entry for both precisions.  FP32 data is
+// widened, multiplied in FP64 and rounded once; the compensated FP32 product
+// (tmul) leaves a rounding bias that grows the norm by about 1e-9 per pass when
+// the multiplier is a nontrivial phase, which accumulates into mass and energy
+// drift over a run.
+__device__ __forceinline__ cplx<double> pmul(cplx<double> a, cplx<double> m) { return cmul(a, m); }
+__device__ __forceinline__ cplx<float> pmul(cplx<float> a, cplx<double> m) {
+  const double x = a.x, y = a.y;
+  return mk(float(fma(x, m.x, -y * m.y)), float(fma(x, m.y, y * m.x)));
+}
+
 // ---------------------------------------------------------------------------
 // Compile-time cos/sin of 2*pi*m/R.  The angle is reduced exactly in integers
 // to [0, pi/4] and evaluated with a Taylor series in double (error ~1 ulp).

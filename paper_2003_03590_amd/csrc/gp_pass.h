@@ -60,7 +60,7 @@ struct PassArgs {
   const RunPtrs* batch;    // grouped launch over runs of one size, or null
   const void* in;          // input field (complex, working precision)
   void* out;               // output field (may equal in)
-  const void* mult;        // PROP: multiplier in position order (N_j Tab<Real> entries)
+  const void* mult;        // PROP: multiplier in lane order (N_j FP64 complex entries)
   const void* tw;          // per-stage twiddles W_{R M}^{lo k} (Tab<Real> entries, layout above)
   const void* aux;         // PRO_ADJ_NL: forward state phi at the same points
   const double* ksq;       // k_j^2 in position order (kinetic accumulation)
@@ -302,7 +302,7 @@ __global__ __launch_bounds__(S::THREADS) void axis_pass(PassArgs a) {
   const long es = a.es;
   const long estep = (long)T * es * (long)sizeof(C);
   const auto tw = gptr<Tab<Real>>(a.tw);
-  const auto mult = gptr<Tab<Real>>(a.mult);
+  const auto mult = gptr<cplx<double>>(a.mult);     // FP64 multipliers for both precisions
 
   // Addressing: element e of this lane in tile tl sits at
   //   bbase + e*T*es   (uniform: first pencil of the tile, scalar registers)
@@ -380,7 +380,7 @@ __global__ __launch_bounds__(S::THREADS) void axis_pass(PassArgs a) {
         for (int r = 0; r < S::rad(L); ++r)
 #pragma unroll
           for (int j = 0; j < B; ++j)
-            v[j + B * r] = tmul(v[j + B * r], tab_at(mult, r * (S::N / S::rad(L)) + t + T * j));
+            v[j + B * r] = pmul(v[j + B * r], tab_at(mult, r * (S::N / S::rad(L)) + t + T * j));
         inverse_all<Real, S, KIND, L>(v, lds, t, col, tw);
       } else {  // FWD: reorder to natural frequency order
         if constexpr (S::NS > 1) exchange<Real, S, KIND, L, -1>(lds, v, t, col);

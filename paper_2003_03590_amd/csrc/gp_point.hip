@@ -88,12 +88,12 @@ template <class Real>
 __global__ void k_mult3(void* f, int nx, int ny, int nz, const void* mx, const void* my, const void* mz) {
   const long n = (long)nx * ny * nz;
   cplx<Real>* p = reinterpret_cast<cplx<Real>*>(f);
-  const Tab<Real>* tx = reinterpret_cast<const Tab<Real>*>(mx);
-  const Tab<Real>* ty = reinterpret_cast<const Tab<Real>*>(my);
-  const Tab<Real>* tz = reinterpret_cast<const Tab<Real>*>(mz);
+  const cplx<double>* tx = reinterpret_cast<const cplx<double>*>(mx);
+  const cplx<double>* ty = reinterpret_cast<const cplx<double>*>(my);
+  const cplx<double>* tz = reinterpret_cast<const cplx<double>*>(mz);
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
     const int ix = (int)(i % nx), iy = (int)((i / nx) % ny), iz = (int)(i / ((long)nx * ny));
-    p[i] = tmul(tmul(tmul(p[i], tx[ix]), ty[iy]), tz[iz]);
+    p[i] = pmul(p[i], cmul(cmul(tx[ix], ty[iy]), tz[iz]));      // product of the factors in FP64
   }
 }
 

@@ -124,10 +124,10 @@ struct Axis {
   unsigned blocks = 0;
   // device tables (working precision unless noted)
   void* tw = nullptr;
-  void* mult[NTAU] = {};    // exp(-i alpha k^2 tau)/n, position order
-  void* deriv = nullptr;    // i k~/n, position order
+  void* mult[NTAU] = {};    // exp(-i alpha k^2 tau)/n, lane order, FP64 complex
+  void* deriv = nullptr;    // i k~/n, lane order, FP64 complex
   double* ksq = nullptr;    // k^2, position order (double)
-  void* nat[NTAU] = {};     // exp(-i alpha k^2 tau)/n, natural order
+  void* nat[NTAU] = {};     // exp(-i alpha k^2 tau)/n, natural order, FP64 complex
 };
 
 }  // namespace
@@ -230,6 +230,15 @@ gp_status upload_cplx(gp_plan_s* p, void** dst, const std::vector<double>& reim)
   return GP_OK;
 }
 
+// upload a complex FP64 table as FP64 complex entries for either precision (the
+// multipliers applied between forward and inverse transforms)
+gp_status upload_c128(gp_plan_s* p, void** dst, const std::vector<double>& reim) {
+  gp_status st = dev_alloc(p, dst, reim.size() * sizeof(double));
+  if (st != GP_OK) return st;
+  HIPCHK(p, hipMemcpy(*dst, reim.data(), reim.size() * sizeof(double), hipMemcpyHostToDevice));
+  return GP_OK;
+}
+
 gp_status upload_f64(gp_plan_s* p, double** dst, const std::vector<double>& v) {
   gp_status st = dev_alloc(p, (void**)dst, v.size() * sizeof(double));
   if (st != GP_OK) return st;
@@ -279,8 +288,8 @@ gp_status build_tables(gp_plan_s* p, int a) {
       mp[2 * pos[k]] = c; mp[2 * pos[k] + 1] = s;
       mn[2 * k] = c; mn[2 * k + 1] = s;
     }
-    if ((st = upload_cplx(p, &A.mult[t], mp)) != GP_OK) return st;
-    if ((st = upload_cplx(p, &A.nat[t], mn)) != GP_OK) return st;
+    if ((st = upload_c128(p, &A.mult[t], mp)) != GP_OK) return st;
+    if ((st = upload_c128(p, &A.nat[t], mn)) != GP_OK) return st;
   }
   std::vector<double> dv(2 * n), kq(n);
   for (int k = 0; k < n; ++k) {
@@ -289,7 +298,7 @@ gp_status build_tables(gp_plan_s* p, int a) {
     dv[2 * pos[k]] = 0.0; dv[2 * pos[k] + 1] = (double)k1 / n;       // i k~ / n
     kq[pos[k]] = (double)kf * kf;
   }
-  if ((st = upload_cplx(p, &A.deriv, dv)) != GP_OK) return st;
+  if ((st = upload_c128(p, &A.deriv, dv)) != GP_OK) return st;
   if ((st = upload_f64(p, &A.ksq, kq)) != GP_OK) return st;
   return GP_OK;
 }
@@ -668,7 +677,7 @@ gp_status gp_substep_linear(gp_plan_t* p, void* psi, int32_t axis, double s) {
     m[2 * ps + 1] = -std::sin(ph) / n;
   }
   void*& tab = p->substep_tables[{axis, s}];
-  if (!tab && (st = upload_cplx(p, &tab, m)) != GP_OK) return st;
+  if (!tab && (st = upload_c128(p, &tab, m)) != GP_OK) return st;
   return pass(p, axis, V_PROP, psi, psi, tab);
 }
 
