@@ -182,19 +182,27 @@ GP_API gp_status gp_energies_batch(gp_plan_t* p, void* const* psis, void* work, 
 /* Message of the last non-OK status on this thread ("" if none). */
 GP_API const char* gp_last_error(void);
 
-/* Name of the compiled FFT schedule used for an axis, e.g. "N=256 T=16 W=8 R=16x16". */
+/* Name of the compiled FFT schedule used for an axis, e.g. "N=256 T=16 W=8 R=16x16".
+ * axis 3 names the xy choice: "xy: separate passes" or "xy: plane N=.. T=..". */
 GP_API const char* gp_schedule_name(const gp_plan_t* p, int32_t axis);
 
 /* Number of compiled schedule variants for an axis length and precision, and
  * selection of one of them for an axis of a plan.  Selecting rebuilds that
- * axis's tables (their order follows the schedule's radices); synchronizes. */
+ * axis's tables (their order follows the schedule's radices); synchronizes.
+ * axis 3 selects how the two in-plane sub-steps run in gp_step_n and
+ * gp_step_n_batch: variant 0 = separate x and y passes, 1 = one xy-plane pass per
+ * z-plane (both sub-steps on chip, psi read and written once; the x and y factors
+ * commute, time-evolution section).  Variant 1 needs nx == ny with a compiled
+ * plane length (complex64: 16..96, complex128: 16..64); otherwise
+ * GP_ERR_UNSUPPORTED. */
 GP_API int32_t gp_variant_count(int32_t n, int32_t prec);
 GP_API gp_status gp_select_variant(gp_plan_t* p, int32_t axis, int32_t variant);
 
 /* Autotuner: for every axis of the plan (every size group of a batch plan),
  * time `reps` launches of each compiled schedule variant on `scratch` (dev, one
  * state of the plan's largest run; its contents are overwritten) with HIP
- * events, and keep the fastest.  cache_path (may be NULL): a JSON file of
+ * events, and keep the fastest; then the xy choice (axis 3), timed with as many
+ * runs per launch as the size group holds.  cache_path (may be NULL): a JSON file of
  * earlier choices keyed by GPU architecture, precision, grid shape and axis;
  * cached choices are applied without timing and new ones are added.
  * Synchronizes.  A batch plan re-records its graph on the next step call. */

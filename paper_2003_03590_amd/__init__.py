@@ -116,7 +116,7 @@ class Plan:
         scratch = _torch().zeros(self.shape, dtype=self.dtype, device=self.device)
         _check(lib().gp_autotune(self._h, C.c_void_p(_ptr(scratch)), int(reps),
                                  cache.encode() if cache else None))
-        return [self.schedule(a) for a in range(3)]
+        return [self.schedule(a) for a in range(4)]
 
     # ---------------------------------------------------------------- method
     def init_phase(self, theta, out=None):
@@ -245,6 +245,11 @@ class BatchPlan:
     def step_n(self, states, nsteps: int):
         _check(lib().gp_step_n_batch(self._h, self._ptrs(states), int(nsteps)))
         return states
+
+    def select_xy(self, variant: int):
+        """0: separate x and y passes; 1: one xy-plane pass for every run with a plane
+        schedule (the next step call records a new graph)."""
+        _check(lib().gp_select_variant(self._h, 3, int(variant)))
 
     def autotune(self, reps: int = 5, cache: str | None = None):
         """Autotune each size group on a scratch state of the largest run."""

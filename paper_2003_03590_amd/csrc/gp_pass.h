@@ -53,6 +53,7 @@ struct RunPtrs {
   const void* in;
   void* out;
   const void* mult;
+  const void* mult2;       // plane pass: the y multipliers (mult holds the x ones)
   double nl_coef;
 };
 

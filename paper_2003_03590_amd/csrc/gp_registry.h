@@ -5,6 +5,7 @@
 #include <vector>
 
 #include "gp_pass.h"
+#include "gp_plane.h"
 
 namespace gpk {
 
@@ -18,6 +19,32 @@ struct PassEntry {
 };
 
 std::vector<PassEntry>& registry();
+
+// xy-plane schedules (one per grid length and precision; W = N)
+struct PlaneEntry {
+  int n, prec;
+  int T, NS, threads;
+  int radix[3];
+  PlaneLauncher fn[2];           // [0] propagator, [1] with the nonlinear prologue
+};
+
+std::vector<PlaneEntry>& plane_registry();
+
+struct PlaneRegistrar {
+  explicit PlaneRegistrar(const PlaneEntry& e) { plane_registry().push_back(e); }
+};
+
+template <class Real, class S>
+PlaneEntry make_plane_entry(int prec) {
+  static_assert(S::THREADS % 64 == 0, "workgroup must be whole wavefronts");
+  PlaneEntry e{};
+  e.n = S::N; e.prec = prec;
+  e.T = S::T; e.NS = S::NS; e.threads = S::THREADS;
+  for (int s = 0; s < 3; ++s) e.radix[s] = s < S::NS ? S::rad(s) : 1;
+  e.fn[0] = &launch_plane<Real, S, PRO_NONE>;
+  e.fn[1] = &launch_plane<Real, S, PRO_NL>;
+  return e;
+}
 
 struct Registrar {
   explicit Registrar(const PassEntry& e) { registry().push_back(e); }
@@ -54,3 +81,7 @@ PassEntry make_entry(int prec, int variant) {
 #define GPK_SCHED(REAL, PREC, VAR, N, T, W, R0, R1, R2)                                         \
   static ::gpk::Registrar GPK_CAT(gpk_reg_, __LINE__)(                                          \
       ::gpk::make_entry<REAL, ::gpk::Sched<N, T, W, R0, R1, R2>>(PREC, VAR));
+// GPK_PLANE(real, prec, N, T, R0, R1, R2): xy-plane schedule with W = N
+#define GPK_PLANE(REAL, PREC, N, T, R0, R1, R2)                                                  \
+  static ::gpk::PlaneRegistrar GPK_CAT(gpk_plane_, __LINE__)(                                    \
+      ::gpk::make_plane_entry<REAL, ::gpk::Sched<N, T, N, R0, R1, R2>>(PREC));

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <string>
@@ -20,6 +21,11 @@ namespace gpk {
 
 std::vector<PassEntry>& registry() {
   static std::vector<PassEntry> r;
+  return r;
+}
+
+std::vector<PlaneEntry>& plane_registry() {
+  static std::vector<PlaneEntry> r;
   return r;
 }
 
@@ -162,7 +168,17 @@ struct gp_plan_s {
   double* h_result = nullptr;      // pinned mirror
   bool broken = false;
   bool own_stream = false;         // stream created by the plan (batch plans on the null stream)
-  std::string sched_name[3];
+  std::string sched_name[4];       // x, y, z axis schedules; [3]: the xy-plane choice
+  // xy-plane pass (x and y sub-steps fused; needs nx == ny with a compiled plane schedule)
+  struct Plane {
+    const PlaneEntry* e = nullptr;
+    bool on = false;
+    void* tw = nullptr;
+    void* mx[NTAU] = {};
+    void* my[NTAU] = {};
+  } plane;
+  RunPtrs* d_tune_ptrs = nullptr;  // autotuner: grouped timing launches
+  size_t n_tune_ptrs = 0;
   // ensemble
   bool is_batch = false;
   std::vector<gp_plan_s*> runs;
@@ -303,6 +319,46 @@ gp_status build_tables(gp_plan_s* p, int a) {
   return GP_OK;
 }
 
+const PlaneEntry* find_plane(int n, int prec) {
+  for (const auto& e : plane_registry())
+    if (e.n == n && e.prec == prec) return &e;
+  return nullptr;
+}
+
+// a plane schedule described as an axis schedule (for the table-order helpers)
+PassEntry plane_as_entry(const PlaneEntry& pe) {
+  PassEntry e{};
+  e.n = pe.n; e.prec = pe.prec; e.T = pe.T; e.W = pe.n; e.NS = pe.NS; e.threads = pe.threads;
+  for (int i = 0; i < 3; ++i) e.radix[i] = pe.radix[i];
+  return e;
+}
+
+// twiddles and x/y multipliers of the plane schedule (built once per plan; with
+// nx == ny and one alpha the x and y multipliers are the same table)
+gp_status build_plane_tables(gp_plan_s* p) {
+  auto& P = p->plane;
+  if (P.tw) return GP_OK;
+  const PassEntry e = plane_as_entry(*P.e);
+  gp_status st;
+  if ((st = upload_cplx(p, &P.tw, stage_twiddles(e))) != GP_OK) return st;
+  const double alpha = p->d.alpha, dt = p->d.dt;
+  const double taus[NTAU] = {0.5 * dt, dt, -0.5 * dt, -dt};
+  const int n = e.n;
+  for (int t = 0; t < NTAU; ++t) {
+    std::vector<double> m(2 * n);
+    for (int k = 0; k < n; ++k) {
+      const double kk = (double)kfreq(k, n);
+      const double ph = alpha * kk * kk * taus[t];
+      const int i = tab_idx(e, k);
+      m[2 * i] = std::cos(ph) / n;
+      m[2 * i + 1] = -std::sin(ph) / n;
+    }
+    if ((st = upload_c128(p, &P.mx[t], m)) != GP_OK) return st;
+    P.my[t] = P.mx[t];
+  }
+  return GP_OK;
+}
+
 int shell_of_host(long k2) {
   const long q = 4 * k2;
   long r = (long)std::sqrt((double)q);
@@ -326,6 +382,8 @@ gp_status plan_init(gp_plan_s* p, const gp_desc* d, hipStream_t stream) {
     if ((st = setup_axis(p, a, 0)) != GP_OK) return st;
     if ((st = build_tables(p, a)) != GP_OK) return st;
   }
+  p->plane.e = (d->n[0] == d->n[1] && d->n[0] > 1) ? find_plane(d->n[0], p->prec) : nullptr;
+  p->sched_name[3] = "xy: separate passes";
   // reduction partials
   const long kin_n = (long)p->ax[0].blocks + p->ax[1].blocks + p->ax[2].blocks;
   if ((st = dev_alloc(p, (void**)&p->kin_part, std::max(1L, kin_n) * sizeof(double))) != GP_OK) return st;
@@ -419,6 +477,14 @@ gp_status linear_all(gp_plan_s* p, void* psi, int tau, bool with_nl, double nl) 
   if (c < 0) {   // 1x1x1 grid: only the nonlinear rotation acts (k = 0)
     if (with_nl) { launch_nonlinear(p->prec, psi, p->ntot, nl, p->stream); return check_launch(p); }
     return GP_OK;
+  }
+  if (p->plane.on) {          // x and y in one plane pass (nonlinear prologue there), then z
+    PlaneArgs g{};
+    g.in = psi; g.out = psi; g.multx = p->plane.mx[tau]; g.multy = p->plane.my[tau];
+    g.tw = p->plane.tw; g.nl_coef = nl;
+    p->plane.e->fn[with_nl ? 1 : 0](g, (unsigned)p->d.n[2], 1, p->stream);
+    if ((st = check_launch(p)) != GP_OK) return st;
+    return p->ax[2].n > 1 ? pass(p, 2, V_PROP, psi, psi, p->ax[2].mult[tau]) : GP_OK;
   }
   for (int a = 0; a < 3; ++a) {
     if (p->ax[a].n == 1) continue;
@@ -587,7 +653,7 @@ int32_t gp_nshell(const gp_plan_t* p) { return p ? p->nshell : 0; }
 const char* gp_last_error(void) { return g_err.c_str(); }
 
 const char* gp_schedule_name(const gp_plan_t* p, int32_t axis) {
-  if (!p || axis < 0 || axis > 2) return "";
+  if (!p || axis < 0 || axis > 3) return "";
   return p->sched_name[axis].c_str();
 }
 
@@ -600,6 +666,35 @@ int32_t gp_variant_count(int32_t n, int32_t prec) {
 gp_status gp_select_variant(gp_plan_t* p, int32_t axis, int32_t variant) {
   gp_status st = usable(p);
   if (st != GP_OK) return st;
+  if (p->is_batch) {   // the xy choice for every run that has a plane schedule
+    if (axis != 3) return fail(GP_ERR_STATE, "batch plan: axis schedules are chosen by gp_autotune");
+    for (auto* r : p->runs)
+      if (r->plane.e || variant == 0)
+        if ((st = gp_select_variant(r, 3, variant)) != GP_OK) return st;
+    if (p->graph_exec) { (void)hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
+    if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+    p->graph_steps = 0;
+    return GP_OK;
+  }
+  if (axis == 3) {   // xy plane: 0 = separate x and y passes, 1 = one plane pass
+    if (variant == 0) {
+      p->plane.on = false;
+      p->sched_name[3] = "xy: separate passes";
+      return GP_OK;
+    }
+    if (variant != 1) return fail(GP_ERR_ARG, "xy variant %d (0 = separate passes, 1 = plane pass)", variant);
+    if (!p->plane.e)
+      return fail(GP_ERR_UNSUPPORTED, "no xy-plane schedule for %dx%d (needs nx == ny with a compiled plane length)",
+                  p->d.n[0], p->d.n[1]);
+    HIPCHK(p, p->stream ? hipStreamSynchronize(p->stream) : hipDeviceSynchronize());
+    if ((st = build_plane_tables(p)) != GP_OK) return st;
+    p->plane.on = true;
+    char nm[128];
+    snprintf(nm, sizeof nm, "xy: plane N=%d T=%d R=%dx%dx%d", p->plane.e->n, p->plane.e->T, p->plane.e->radix[0],
+             p->plane.e->radix[1], p->plane.e->radix[2]);
+    p->sched_name[3] = nm;
+    return GP_OK;
+  }
   if (axis < 0 || axis > 2) return fail(GP_ERR_ARG, "axis %d", axis);
   if (p->ax[axis].n == 1) return variant == 0 ? GP_OK : fail(GP_ERR_ARG, "axis of length 1 has one variant");
   const PassEntry* e = find_entry(p->ax[axis].n, p->prec, variant);
@@ -954,6 +1049,10 @@ static gp_status batch_record(gp_plan_s* p, void* const* psis, int64_t nsteps) {
           e.out = psis[g.members[i]];
           e.mult = r->ax[a].mult[t == 0 ? th : tf];
           e.nl_coef = r->d.beta * (back ? -r->d.dt : r->d.dt);
+          if (a == 0 && r->plane.on) {   // the x slot carries the plane pass's x and y tables
+            e.mult = r->plane.mx[t == 0 ? th : tf];
+            e.mult2 = r->plane.my[t == 0 ? th : tf];
+          }
         }
     if (g.nptrs < h.size()) {
       if (g.d_ptrs) (void)hipFree(g.d_ptrs);
@@ -976,10 +1075,27 @@ static gp_status batch_record(gp_plan_s* p, void* const* psis, int64_t nsteps) {
     args.npencils = A.npencils; args.inner = A.inner; args.outer = A.outer; args.es = A.es;
     A.e->fn[A.kind][var](args, A.blocks, (unsigned)m, p->stream);
   };
+  auto grouped_plane = [&](const gp_plan_s::Group& g, int t, bool nl) -> void {
+    gp_plan_s* r = p->runs[g.members[0]];
+    const size_t m = g.members.size();
+    PlaneArgs args{};
+    args.batch = g.d_ptrs + (0 * 2 + t) * m;
+    args.tw = r->plane.tw;
+    r->plane.e->fn[nl ? 1 : 0](args, (unsigned)r->d.n[2], (unsigned)m, p->stream);
+  };
   for (const auto& g : p->groups) {
     gp_plan_s* r0 = p->runs[g.members[0]];
     const int c = first_real_axis(r0);
     if (c < 0) continue;     // 1x1x1 runs are not batched
+    if (r0->plane.on) {      // every member of the group made the same choice
+      grouped_plane(g, 0, false);
+      if (r0->ax[2].n > 1) grouped(g, 2, 0, V_PROP);
+      for (int64_t s = 0; s < n; ++s) {
+        grouped_plane(g, s + 1 < n ? 1 : 0, true);
+        if (r0->ax[2].n > 1) grouped(g, 2, s + 1 < n ? 1 : 0, V_PROP);
+      }
+      continue;
+    }
     for (int a = 0; a < 3; ++a) if (r0->ax[a].n > 1) grouped(g, a, 0, V_PROP);
     for (int64_t s = 0; s < n; ++s)
       for (int a = 0; a < 3; ++a)
@@ -1107,8 +1223,68 @@ static gp_status time_axis(gp_plan_s* p, int axis, void* scratch, int reps, doub
   return st;
 }
 
+// time `reps` calls of launch() on the plan's stream (microseconds per call)
+static gp_status time_calls(gp_plan_s* p, int reps, double* us, const std::function<void()>& launch) {
+  hipEvent_t a, b;
+  HIPCHK(p, hipEventCreate(&a));
+  HIPCHK(p, hipEventCreate(&b));
+  launch();                                    // warm-up
+  (void)hipEventRecord(a, p->stream);
+  for (int r = 0; r < reps; ++r) launch();
+  (void)hipEventRecord(b, p->stream);
+  float ms = 0.f;
+  hipError_t e = hipEventSynchronize(b);
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (e != hipSuccess) { p->broken = true; return fail(GP_ERR_HIP, "event timing: %s", hipGetErrorString(e)); }
+  *us = 1e3 * ms / std::max(1, reps);
+  return check_launch(p);
+}
+
+// xy choice: separate x and y passes against one plane pass, both launched for
+// `runs` copies of the scratch state at once (the ensemble launches a size group
+// together, which changes how well each option fills the GPU; the copies all
+// alias `scratch`, whose contents are undefined afterwards)
+static gp_status tune_xy(gp_plan_s* p, void* scratch, int reps, int runs, int* choice) {
+  gp_status st;
+  *choice = 0;
+  if (!p->plane.e || p->ax[0].n == 1) return GP_OK;
+  if ((st = build_plane_tables(p)) != GP_OK) return st;
+  const size_t need = 3 * (size_t)runs;
+  if (p->n_tune_ptrs < need) {
+    if ((st = dev_alloc(p, (void**)&p->d_tune_ptrs, need * sizeof(RunPtrs))) != GP_OK) return st;
+    p->n_tune_ptrs = need;
+  }
+  std::vector<RunPtrs> h(need);
+  for (int i = 0; i < runs; ++i) {
+    h[i] = RunPtrs{scratch, scratch, p->ax[0].mult[TAU_DT], nullptr, 0.0};
+    h[runs + i] = RunPtrs{scratch, scratch, p->ax[1].mult[TAU_DT], nullptr, 0.0};
+    h[2 * runs + i] = RunPtrs{scratch, scratch, p->plane.mx[TAU_DT], p->plane.my[TAU_DT], 0.0};
+  }
+  HIPCHK(p, hipMemcpy(p->d_tune_ptrs, h.data(), need * sizeof(RunPtrs), hipMemcpyHostToDevice));
+  auto axis_launch = [&](int a, const RunPtrs* ptrs) {
+    const Axis& A = p->ax[a];
+    PassArgs g{};
+    g.batch = ptrs; g.tw = A.tw; g.ksq = A.ksq; g.scale = 1.0;
+    g.npencils = A.npencils; g.inner = A.inner; g.outer = A.outer; g.es = A.es;
+    A.e->fn[A.kind][V_PROP](g, A.blocks, (unsigned)runs, p->stream);
+  };
+  double t_sep = 0, t_plane = 0;
+  if ((st = time_calls(p, reps, &t_sep, [&] { axis_launch(0, p->d_tune_ptrs); axis_launch(1, p->d_tune_ptrs + runs); })) != GP_OK)
+    return st;
+  if ((st = time_calls(p, reps, &t_plane, [&] {
+         PlaneArgs g{};
+         g.batch = p->d_tune_ptrs + 2 * runs; g.tw = p->plane.tw;
+         p->plane.e->fn[0](g, (unsigned)p->d.n[2], (unsigned)runs, p->stream);
+       })) != GP_OK)
+    return st;
+  *choice = t_plane < t_sep ? 1 : 0;
+  return GP_OK;
+}
+
 static gp_status tune_plan(gp_plan_s* p, void* scratch, int reps, std::map<std::string, int>& cache,
-                           const std::string& arch, int chosen[3]) {
+                           const std::string& arch, int chosen[4], int runs) {
   gp_status st;
   for (int a = 0; a < 3; ++a) {
     chosen[a] = 0;
@@ -1134,6 +1310,20 @@ static gp_status tune_plan(gp_plan_s* p, void* scratch, int reps, std::map<std::
     cache[key] = bestv;
     chosen[a] = bestv;
   }
+  chosen[3] = 0;
+  if (p->plane.e) {
+    char b[32];
+    snprintf(b, sizeof b, "/r%d", runs);
+    const std::string key = tune_key(arch, p, 3) + b;
+    auto it = cache.find(key);
+    if (it != cache.end() && (it->second == 0 || it->second == 1)) {
+      chosen[3] = it->second;
+    } else {
+      if ((st = tune_xy(p, scratch, reps, runs, &chosen[3])) != GP_OK) return st;
+      cache[key] = chosen[3];
+    }
+    if ((st = gp_select_variant(p, 3, chosen[3])) != GP_OK) return st;
+  }
   return GP_OK;
 }
 
@@ -1145,16 +1335,18 @@ gp_status gp_autotune(gp_plan_t* p, void* scratch, int32_t reps, const char* cac
   auto cache = read_cache(cache_path);
   const std::string arch = arch_name();
   if (!p->is_batch) {
-    int chosen[3];
-    if ((st = tune_plan(p, scratch, reps, cache, arch, chosen)) != GP_OK) return st;
+    int chosen[4];
+    if ((st = tune_plan(p, scratch, reps, cache, arch, chosen, 1)) != GP_OK) return st;
   } else {
     for (auto& g : p->groups) {
       gp_plan_s* r0 = p->runs[g.members[0]];
-      int chosen[3];
-      if ((st = tune_plan(r0, scratch, reps, cache, arch, chosen)) != GP_OK) return st;
+      int chosen[4];
+      if ((st = tune_plan(r0, scratch, reps, cache, arch, chosen, (int)g.members.size())) != GP_OK) return st;
       for (size_t i = 1; i < g.members.size(); ++i)
-        for (int a = 0; a < 3; ++a)
+        for (int a = 0; a < 4; ++a) {
+          if (a == 3 && !p->runs[g.members[i]]->plane.e) continue;
           if ((st = gp_select_variant(p->runs[g.members[i]], a, chosen[a])) != GP_OK) return st;
+        }
     }
     // kernels and tables changed: the recorded graph is stale
     if (p->graph_exec) { (void)hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }

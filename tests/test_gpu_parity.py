@@ -80,6 +80,57 @@ def test_step_n_matches_literal_oracle(shape, steps):
     assert rel_l2(psi.cpu().numpy(), ref) < 1e-12
 
 
+PLANE_CASES = [((16, 16, 16), "c64"), ((32, 32, 8), "c64"), ((48, 48, 6), "c64"), ((64, 64, 64), "c64"),
+               ((96, 96, 4), "c64"), ((16, 16, 3), "c128"), ((32, 32, 32), "c128"), ((48, 48, 12), "c128"),
+               ((64, 64, 8), "c128"), ((64, 64, 1), "c128")]
+
+
+@pytest.mark.parametrize("shape,prec", PLANE_CASES, ids=lambda v: "x".join(map(str, v)) if isinstance(v, tuple) else v)
+def test_plane_pass_steps_match_oracle(shape, prec):
+    """gp_step_n with the xy-plane pass (both in-plane sub-steps in one kernel, the
+    nonlinear rotation fused in front) against the oracle's literal steps, forward
+    and backward."""
+    nx, ny, nz = shape
+    psi0 = I.random_field((nz, ny, nx), seed=21)
+    plan = _plan(shape, 0.3, 4.0, 0.01, prec)
+    plan.select_variant(3, 1)
+    assert plan.schedule(3).startswith("xy: plane")
+    base = psi0.astype(np.complex64).astype(np.complex128) if prec == "c64" else psi0
+    psi = _to_dev(psi0, prec)
+    plan.step_n(psi, 3)
+    ref = O.evolve(base, 0.3, 4.0, 0.01, 3)
+    tol = 1e-12 if prec == "c128" else 5e-6
+    assert rel_l2(psi.cpu().numpy().astype(np.complex128), ref) < tol
+    plan.step_n(psi, -2)
+    ref = O.evolve(ref, 0.3, 4.0, 0.01, -2)
+    assert rel_l2(psi.cpu().numpy().astype(np.complex128), ref) < 2 * tol
+    plan.select_variant(3, 0)
+    assert plan.schedule(3) == "xy: separate passes"
+
+
+def test_plane_pass_unavailable_shape_is_an_error():
+    import paper_2003_03590_amd as gp
+    plan = _plan((24, 16, 8), 0.3, 4.0, 0.01, "c64")
+    with pytest.raises(gp._lib.GPError):
+        plan.select_variant(3, 1)
+
+
+def test_batch_plane_pass_matches_oracle():
+    """The ensemble graph with the xy-plane pass in every run, replayed."""
+    import paper_2003_03590_amd as gp
+    runs = [dict(n=32, alpha=0.4, beta=2.0, dt=0.01), dict(n=16, alpha=0.3, beta=3.0, dt=0.01),
+            dict(n=32, alpha=0.5, beta=1.0, dt=0.02), dict(n=48, alpha=0.2, beta=3.0, dt=0.01)]
+    bp = gp.BatchPlan(runs, "c128")
+    bp.select_xy(1)
+    refs = [I.random_field(r["n"], seed=90 + i) for i, r in enumerate(runs)]
+    states = [_to_dev(a, "c128") for a in refs]
+    for rep in range(2):
+        bp.step_n(states, 3)
+        for i, r in enumerate(runs):
+            refs[i] = O.evolve(refs[i], r["alpha"], r["beta"], r["dt"], 3)
+            assert rel_l2(states[i].cpu().numpy(), refs[i]) < 1e-12, (rep, i)
+
+
 def test_step_n_negative_is_backward_and_reversible():
     psi0 = I.random_field(16, seed=12)
     plan = _plan(16, 0.6, 2.0, 0.02)
@@ -333,7 +384,9 @@ def test_autotune_and_cache(tmp_path):
     plan = _plan(64, 0.3, 4.0, 0.01, "c64")
     chosen = plan.autotune(reps=2, cache=cache)
     data = json.load(open(cache))
-    assert len(data) == 3 and all(k.split("/")[1] == "c64" for k in data)
+    # three axis schedules and the xy choice (plane pass or separate passes, single run)
+    assert len(data) == 4 and all(k.split("/")[1] == "c64" for k in data)
+    assert any(k.endswith("/a3/r1") for k in data) and len(chosen) == 4
     plan2 = _plan(64, 0.3, 4.0, 0.01, "c64")
     assert plan2.autotune(reps=2, cache=cache) == chosen
     psi0 = I.random_field(64, seed=77)
@@ -347,4 +400,4 @@ def test_autotune_and_cache(tmp_path):
     bp.step_n(sts, 1)
     bp.autotune(reps=2, cache=cache)
     bp.step_n(sts, 1)
-    assert len(json.load(open(cache))) >= 6
+    assert len(json.load(open(cache))) >= 8
