@@ -77,6 +77,18 @@ def srp_fourier_theta(shape, K: int, seed: int, rms: float = 1.0) -> np.ndarray:
 
 
 # ------------------------------------------------------------------ TG
+def tg_velocity(n: int):
+    """Taylor-Green velocity field v_TG (eq. tg3d) on an n^3 grid, as the
+    components [v_z, v_y, v_x] (FP64, each shaped [z][y][x])."""
+    x = grid(n)
+    sx, cx = np.sin(x), np.cos(x)
+    vx = sx[None, None, :] * cx[None, :, None] * cx[:, None, None]
+    vy = -cx[None, None, :] * sx[None, :, None] * cx[:, None, None]
+    vz = np.zeros((n, n, n))
+    return [vz, np.ascontiguousarray(np.broadcast_to(vy, (n, n, n))),
+            np.ascontiguousarray(np.broadcast_to(vx, (n, n, n)))]
+
+
 def tg_psi(n: int, xi: float, exponent: int) -> np.ndarray:
     """Taylor-Green ansatz psi_4^exponent on an n^3 grid (complex128)."""
     x = grid(n)
@@ -207,6 +219,12 @@ WORKLOADS = {
     "adj128": dict(n=128, prec=("c128",), alpha=0.05, beta=40.0, dt=1e-3, steps=400,
                    ic=("srp", dict(K=6, seed=2)), ckpt=20, smin=4, smax=12,
                    fd_h=1e-6, fd_dirs=16, fd_seed0=1000),
+    # Taylor-Green preparation by the imaginary-time (ARGLE) procedure, run TG_aIT
+    # of the paper's TG parameter table: 128^3, alpha = 0.05, beta = 40,
+    # dtau = 1.25e-2, tau_f = 60, ansatz psi_4^[gamma_d/4] with [gamma_d/4] = 3,
+    # xi = sqrt(alpha/beta)
+    "tg128_argle": dict(n=128, prec=("c128",), alpha=0.05, beta=40.0, dtau=1.25e-2, steps=4800,
+                        ic=("tg", dict(xi=math.sqrt(0.05 / 40.0), exponent=3)), velocity="tg"),
     "ens48": dict(runs=[dict(n=64, alpha=0.1, beta=20.0, seed=100 + i) for i in range(32)]
                   + [dict(n=96, alpha=6.4 / 96, beta=30.0, seed=132 + i) for i in range(16)],
                   prec=("c64",), dt=1e-3, steps=300, K=4, diag_every=50),
