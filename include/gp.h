@@ -76,8 +76,11 @@ typedef struct {
  *   e_kin    <|w|^2>/2, w = 2 alpha Im(conj(psi) grad psi)/|psi| = sqrt(rho) v
  *   e_kin_i, e_kin_c   incompressible / compressible parts of e_kin (Helmholtz
  *            split of w; the k = 0 mode counts as incompressible)
- *   e_q      2 alpha^2 <|grad |psi||^2>   e_int  alpha beta <(|psi|^2-1)^2>
- *                                            (eq. scaling-energy-mod-rho)        */
+ *   e_q      <|q|^2>/2, q = 2 alpha Re(conj(psi) grad psi)/|psi| = 2 alpha grad |psi|
+ *            (pointwise from the spectral derivatives of psi, as w; q = w = 0 where
+ *            psi = 0), so e_kin + e_q = 2 alpha^2 sum_k |k~|^2 |c_k|^2 with the
+ *            first-derivative k~ (Nyquist entry 0)
+ *   e_int    alpha beta <(|psi|^2-1)^2>          (eq. scaling-energy-mod-rho)    */
 typedef struct {
   double mass, energy, e_kin, e_kin_i, e_kin_c, e_q, e_int;
 } gp_energy;
@@ -169,6 +172,26 @@ GP_API gp_status gp_adjoint_step_n(gp_plan_t* p, const void* psi_seg_start, void
 
 /* dJ/dtheta = Im(lam0 conj(psi0)) for psi0 = exp(i theta).  dJ_dtheta: dev, N^3 doubles. */
 GP_API gp_status gp_phase_grad(gp_plan_t* p, const void* psi0, const void* lam0, double* dJ_dtheta);
+
+/* Imaginary-time preparation of a driven stationary state (section on stationary
+ * solutions): nsteps steps of the semi-implicit backward Euler scheme
+ * (eq. semi-backward-Euler) for the advective real Ginzburg-Landau equation
+ * (eq. gradient-flow)
+ *   phi_tau = (alpha lap - i v.grad - |v|^2/(4 alpha) + beta - beta |phi|^2) phi,
+ * half of the Laplacian implicit (diagonal in Fourier space), the rest explicit;
+ * alpha, beta from the plan (its dt is not used).  phi: dev, in/out, N^3 complex.
+ * v: dev, three real fields v_x, v_y, v_z of the plan's real precision (FP64 for
+ * GP_C128, FP32 for GP_C64), each N^3 in the [z][y][x] order of phi.  dtau > 0,
+ * nsteps >= 0.  work: dev, gp_work_bytes (four states used).  |k|^2 of the
+ * Laplacian uses N^2/4 at the Nyquist index; first derivatives use 0 there.
+ * Asynchronous on the plan's stream.  Not for batch plans (GP_ERR_STATE). */
+GP_API gp_status gp_argle_step(gp_plan_t* p, void* phi, const void* v, double dtau, int64_t nsteps, void* work);
+
+/* Driven energy per unit volume (eq. energy-num-ext-vel)
+ *   E_v = 2 alpha < alpha |grad phi - i v phi/(2 alpha)|^2 + (beta/2)(|phi|^2 - 1)^2 >,
+ * the quantity the imaginary-time flow decreases.  Arguments as for
+ * gp_argle_step; energy_v: host out.  Synchronizes. */
+GP_API gp_status gp_argle_energy(gp_plan_t* p, const void* phi, const void* v, void* work, double* energy_v);
 
 /* Ensemble: advance run i's state psis[i] (host array of dev pointers) by nsteps.
  * The first call for a given set of pointers and nsteps records a HIP graph;

@@ -162,6 +162,31 @@ class Plan:
         _check(lib().gp_energies(self._h, self._field(psi), C.c_void_p(_ptr(self.work())), C.byref(e)))
         return e.as_dict()
 
+    def _velocity(self, v):
+        """v: (3, Nz, Ny, Nx) real tensor, components (v_x, v_y, v_z), in the plan's
+        real precision on its device."""
+        torch = _torch()
+        rdt = torch.float64 if self.prec == GP_C128 else torch.float32
+        v = v.to(device=self.device, dtype=rdt).contiguous()
+        if tuple(v.shape) != (3,) + tuple(self.shape):
+            raise ValueError(f"velocity must have shape {(3,) + tuple(self.shape)}")
+        return v
+
+    def argle_step(self, phi, v, dtau: float, nsteps: int):
+        """nsteps imaginary-time (ARGLE) steps of phi in place; v as in _velocity."""
+        v = self._velocity(v)
+        _check(lib().gp_argle_step(self._h, self._field(phi, "phi"), C.c_void_p(v.data_ptr()), float(dtau),
+                                   int(nsteps), C.c_void_p(_ptr(self.work()))))
+        return phi
+
+    def argle_energy(self, phi, v) -> float:
+        """Driven energy E_v per unit volume."""
+        v = self._velocity(v)
+        out = C.c_double()
+        _check(lib().gp_argle_energy(self._h, self._field(phi, "phi"), C.c_void_p(v.data_ptr()),
+                                     C.c_void_p(_ptr(self.work())), C.byref(out)))
+        return out.value
+
     def spectra(self, psi):
         out = np.zeros((4, self.nshell), dtype=np.float64)
         e = gp_energy()

@@ -55,6 +55,8 @@ SIGNATURES = {
     "gp_loss_ekin_i_shells": (ST, [P, P, P, C.c_int32, C.c_int32, C.POINTER(C.c_double), P]),
     "gp_adjoint_step_n": (ST, [P, P, P, C.c_int64, P]),
     "gp_phase_grad": (ST, [P, P, P, P]),
+    "gp_argle_step": (ST, [P, P, P, C.c_double, C.c_int64, P]),
+    "gp_argle_energy": (ST, [P, P, P, P, C.POINTER(C.c_double)]),
     "gp_step_n_batch": (ST, [P, PP, C.c_int64]),
     "gp_energies_batch": (ST, [P, PP, P, C.POINTER(C.c_double)]),
     "gp_last_error": (C.c_char_p, []),

@@ -10,10 +10,11 @@ void launch_nonlinear(int prec, void* psi, long n, double coef, hipStream_t st);
 void launch_scale_copy(int prec, const void* in, void* out, long n, double scale, hipStream_t st);
 void launch_mult3(int prec, void* f, int nx, int ny, int nz, const void* mx, const void* my, const void* mz,
                   hipStream_t st);
-void launch_diag_fields(int prec, const void* psi, void* f0, void* f1, void* f2, long n, double alpha,
+void launch_diag_fields(int prec, const void* psi, void* f0, void* f1, void* f2, void* f3, long n, double alpha,
                         double* partial, unsigned blocks, hipStream_t st);
-void launch_spectral(int prec, const void* F0, const void* F1, const void* F2, int nx, int ny, int nz, double alpha,
-                     double beta, int nshell, unsigned blocks, long chunk, double* bins, hipStream_t st);
+void launch_spectral(int prec, const void* F0, const void* F1, const void* F2, const void* F3, int nx, int ny, int nz,
+                     double alpha, double beta, int nshell, unsigned blocks, long chunk, double* bins,
+                     hipStream_t st);
 void launch_segsum(const double* in, long len, int nseg, double* out, hipStream_t st);
 void launch_finalize_diag(const double* red, double w0, double w1, double w2, int nshell, double alpha, double beta,
                           double ntot, double* out, hipStream_t st);
@@ -26,6 +27,12 @@ void launch_loss_lambda1(int prec, const void* psi, void* d0, void* d1, void* d2
 void launch_loss_lambda2(int prec, void* lam, const void* e0, const void* e1, const void* e2, long n,
                          hipStream_t st);
 void launch_phase_grad(int prec, const void* psi0, const void* lam0, double* out, long n, hipStream_t st);
+void launch_argle_explicit(int prec, const void* phi, const void* dx, const void* dy, const void* dz, const void* v,
+                           void* out, long n, double alpha, double beta, hipStream_t st);
+void launch_argle_solve(int prec, void* P, const void* Q, int nx, int ny, int nz, double a, double dtau, double inv_n,
+                        hipStream_t st);
+void launch_argle_energy(int prec, const void* phi, const void* dx, const void* dy, const void* dz, const void* v,
+                         long n, double alpha, double beta, double* partial, unsigned blocks, hipStream_t st);
 void launch_axis_power(int prec, const void* F, long n, long div, int nj, unsigned blocks, long chunk,
                        double* part, hipStream_t st);
 void launch_init_rvr(int prec, const void* pairs, int npairs, double xi, double a1, double a2, double b1, int nx,

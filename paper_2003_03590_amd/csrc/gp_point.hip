@@ -97,13 +97,84 @@ __global__ void k_mult3(void* f, int nx, int ny, int nz, const void* mx, const v
   }
 }
 
+// ----------------------------------------------------- imaginary time (ARGLE)
+// Section on stationary solutions: the advective real Ginzburg-Landau equation
+// (eq. gradient-flow) advanced by the semi-implicit backward Euler scheme
+// (eq. semi-backward-Euler).  v holds three real fields v_x, v_y, v_z of the working
+// precision; d_x, d_y, d_z are the spectral first derivatives of phi.
+
+// explicit part: n = -i v.grad phi + (beta - |v|^2/(4 alpha) - beta |phi|^2) phi
+template <class Real>
+__global__ __launch_bounds__(256) void k_argle_explicit(const void* phi, const void* dx, const void* dy,
+                                                        const void* dz, const void* v, void* out, long n,
+                                                        double alpha, double beta) {
+  const Real* vx = reinterpret_cast<const Real*>(v);
+  const Real* vy = vx + n;
+  const Real* vz = vy + n;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+    const cplx<Real> p = ldc<Real>(phi, i), a = ldc<Real>(dx, i), b = ldc<Real>(dy, i), c = ldc<Real>(dz, i);
+    const double ux = vx[i], uy = vy[i], uz = vz[i];
+    const double gr = ux * a.x + uy * b.x + uz * c.x, gi = ux * a.y + uy * b.y + uz * c.y;   // v.grad phi
+    const double pr = p.x, pi = p.y;
+    const double f = beta - (ux * ux + uy * uy + uz * uz) / (4.0 * alpha) - beta * (pr * pr + pi * pi);
+    stc<Real>(out, i, gi + f * pr, -gr + f * pi);                                             // -i (gr + i gi) + f phi
+  }
+}
+
+// the implicit half of the Laplacian, diagonal in Fourier space, on unnormalised
+// transforms P = F(phi^n), Q = F(n): P <- ((1 - a k^2) P + dtau Q) / ((1 + a k^2) N^3),
+// a = dtau alpha / 2, |k|^2 with the Nyquist entry N^2/4
+template <class Real>
+__global__ __launch_bounds__(256) void k_argle_solve(void* P, const void* Q, int nx, int ny, int nz, double a,
+                                                     double dtau, double inv_n) {
+  const long n = (long)nx * ny * nz;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+    const int ix = (int)(i % nx), iy = (int)((i / nx) % ny), iz = (int)(i / ((long)nx * ny));
+    const double kx = kfreq(ix, nx), ky = kfreq(iy, ny), kz = kfreq(iz, nz);
+    const double k2 = kx * kx + ky * ky + kz * kz;
+    const double num = 1.0 - a * k2, den = inv_n / (1.0 + a * k2);
+    const cplx<Real> p = ldc<Real>(P, i), q = ldc<Real>(Q, i);
+    stc<Real>(P, i, (num * (double)p.x + dtau * (double)q.x) * den, (num * (double)p.y + dtau * (double)q.y) * den);
+  }
+}
+
+// per-workgroup partial sums of alpha |grad phi - i v phi/(2 alpha)|^2 + (beta/2)(|phi|^2 - 1)^2
+// (the integrand of eq. energy-num-ext-vel without its factor 2 alpha / L^3)
+template <class Real>
+__global__ __launch_bounds__(256) void k_argle_energy(const void* phi, const void* dx, const void* dy, const void* dz,
+                                                      const void* v, long n, double alpha, double beta,
+                                                      double* __restrict__ partial) {
+  __shared__ double sh[4];
+  const Real* vx = reinterpret_cast<const Real*>(v);
+  const Real* vy = vx + n;
+  const Real* vz = vy + n;
+  const double h = 0.5 / alpha;
+  Neu acc;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+    const cplx<Real> p = ldc<Real>(phi, i);
+    const cplx<Real> d[3] = {ldc<Real>(dx, i), ldc<Real>(dy, i), ldc<Real>(dz, i)};
+    const double u[3] = {(double)vx[i], (double)vy[i], (double)vz[i]};
+    const double pr = p.x, pi = p.y, rho = pr * pr + pi * pi;
+    double g = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const double re = (double)d[j].x + u[j] * h * pi, im = (double)d[j].y - u[j] * h * pr;   // d_j - i v_j h phi
+      g += re * re + im * im;
+    }
+    acc.add(alpha * g + 0.5 * beta * (rho - 1.0) * (rho - 1.0));
+  }
+  const double tot = block_sum256(acc.val(), sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
 // ----------------------------------------------------------------- diagnostics
 // In: psi and its spectral derivatives d0 = d/dx, d1 = d/dy, d2 = d/dz (in f0, f1, f2).
-// Out (in place): f0 = w_x + i w_y, f1 = w_z + i |psi|, f2 = (|psi|^2 - 1) + 0i,
-// w = 2 alpha Im(conj(psi) grad psi)/|psi| (0 where psi = 0).
+// Out (in place): f0 = w_x + i w_y, f1 = w_z + i q_x, f2 = q_y + i q_z, f3 = (|psi|^2 - 1) + 0i,
+// w = 2 alpha Im(conj(psi) grad psi)/|psi| and q = 2 alpha Re(conj(psi) grad psi)/|psi|
+// (= 2 alpha grad sqrt(rho)); both 0 where psi = 0.
 // Partials [quantity][block]: sum rho, sum (rho-1)^2, sum |w|^2.
 template <class Real>
-__global__ __launch_bounds__(256) void k_diag_fields(const void* psi, void* f0, void* f1, void* f2, long n,
+__global__ __launch_bounds__(256) void k_diag_fields(const void* psi, void* f0, void* f1, void* f2, void* f3, long n,
                                                      double alpha, double* __restrict__ partial) {
   __shared__ double sh[4];
   Neu a0, a1, a2;
@@ -113,16 +184,20 @@ __global__ __launch_bounds__(256) void k_diag_fields(const void* psi, void* f0, 
     const double pr = p.x, pi = p.y;
     const double rho = pr * pr + pi * pi;
     const double amp = sqrt(rho);
-    double wx = 0, wy = 0, wz = 0;
+    double wx = 0, wy = 0, wz = 0, qx = 0, qy = 0, qz = 0;
     if (amp > 0.0) {
       const double f = 2.0 * alpha / amp;
       wx = f * (pr * (double)dx.y - pi * (double)dx.x);
       wy = f * (pr * (double)dy.y - pi * (double)dy.x);
       wz = f * (pr * (double)dz.y - pi * (double)dz.x);
+      qx = f * (pr * (double)dx.x + pi * (double)dx.y);
+      qy = f * (pr * (double)dy.x + pi * (double)dy.y);
+      qz = f * (pr * (double)dz.x + pi * (double)dz.y);
     }
     stc<Real>(f0, i, wx, wy);
-    stc<Real>(f1, i, wz, amp);
-    stc<Real>(f2, i, rho - 1.0, 0.0);
+    stc<Real>(f1, i, wz, qx);
+    stc<Real>(f2, i, qy, qz);
+    stc<Real>(f3, i, rho - 1.0, 0.0);
     a0.add(rho);
     a1.add((rho - 1.0) * (rho - 1.0));
     a2.add(wx * wx + wy * wy + wz * wz);
@@ -137,16 +212,16 @@ __global__ __launch_bounds__(256) void k_diag_fields(const void* psi, void* f0, 
   }
 }
 
-// Shell binning of the hydrodynamic spectra.  F0 = FFT(w_x + i w_y),
-// F1 = FFT(w_z + i |psi|), F2 = FFT(rho - 1) (unnormalised, natural order).
-// Per k: unpack the real-field transforms with the mirror -k, normalise by
-// 1/Ntot, split w into compressible (parallel to k) and incompressible parts,
-// and add 1/2|w^i|^2, 1/2|w^c|^2, 2 alpha^2 |k~|^2 |a|^2, alpha beta |b|^2 to
-// shell round(|k|).  One wavefront per workgroup; bins live in LDS.
+// Shell binning of the hydrodynamic spectra.  F0 = FFT(w_x + i w_y), F1 = FFT(w_z + i q_x),
+// F2 = FFT(q_y + i q_z), F3 = FFT(rho - 1) (unnormalised, natural order).  Per k: unpack
+// the real-field transforms with the mirror -k, normalise by 1/Ntot, split w into
+// compressible (parallel to k) and incompressible parts, and add 1/2|w^i|^2, 1/2|w^c|^2,
+// 1/2|q|^2, alpha beta |b|^2 to shell round(|k|).  One wavefront per workgroup; bins
+// live in LDS.
 template <class Real>
-__global__ __launch_bounds__(64) void k_spectral(const void* F0, const void* F1, const void* F2, int nx, int ny,
-                                                 int nz, double alpha, double beta, int nshell, long chunk,
-                                                 double* __restrict__ bins_partial) {
+__global__ __launch_bounds__(64) void k_spectral(const void* F0, const void* F1, const void* F2, const void* F3,
+                                                 int nx, int ny, int nz, double alpha, double beta, int nshell,
+                                                 long chunk, double* __restrict__ bins_partial) {
   extern __shared__ double bins[];            // [4][nshell]
   for (int i = threadIdx.x; i < 4 * nshell; i += 64) bins[i] = 0.0;
   __syncthreads();
@@ -160,12 +235,15 @@ __global__ __launch_bounds__(64) void k_spectral(const void* F0, const void* F1,
     const cplx<Real> z0 = ldc<Real>(F0, i), z0m = ldc<Real>(F0, m);
     const cplx<Real> z1 = ldc<Real>(F1, i), z1m = ldc<Real>(F1, m);
     const cplx<Real> z2 = ldc<Real>(F2, i), z2m = ldc<Real>(F2, m);
+    const cplx<Real> z3 = ldc<Real>(F3, i), z3m = ldc<Real>(F3, m);
     // A = (Z + conj Zm)/2, B = (Z - conj Zm)/(2i)
     const double wxr = 0.5 * ((double)z0.x + z0m.x) * inv, wxi = 0.5 * ((double)z0.y - z0m.y) * inv;
     const double wyr = 0.5 * ((double)z0.y + z0m.y) * inv, wyi = -0.5 * ((double)z0.x - z0m.x) * inv;
     const double wzr = 0.5 * ((double)z1.x + z1m.x) * inv, wzi = 0.5 * ((double)z1.y - z1m.y) * inv;
-    const double ar = 0.5 * ((double)z1.y + z1m.y) * inv, ai = -0.5 * ((double)z1.x - z1m.x) * inv;
-    const double br = 0.5 * ((double)z2.x + z2m.x) * inv, bi = 0.5 * ((double)z2.y - z2m.y) * inv;
+    const double qxr = 0.5 * ((double)z1.y + z1m.y) * inv, qxi = -0.5 * ((double)z1.x - z1m.x) * inv;
+    const double qyr = 0.5 * ((double)z2.x + z2m.x) * inv, qyi = 0.5 * ((double)z2.y - z2m.y) * inv;
+    const double qzr = 0.5 * ((double)z2.y + z2m.y) * inv, qzi = -0.5 * ((double)z2.x - z2m.x) * inv;
+    const double br = 0.5 * ((double)z3.x + z3m.x) * inv, bi = 0.5 * ((double)z3.y - z3m.y) * inv;
     const int kx = kfreq(ix, nx), ky = kfreq(iy, ny), kz = kfreq(iz, nz);
     const long k2 = (long)kx * kx + (long)ky * ky + (long)kz * kz;
     double cr = 0, ci = 0;
@@ -177,8 +255,7 @@ __global__ __launch_bounds__(64) void k_spectral(const void* F0, const void* F1,
     const double ec = 0.5 * (cxr * cxr + cxi * cxi + cyr * cyr + cyi * cyi + czr * czr + czi * czi);
     const double ixr = wxr - cxr, ixi = wxi - cxi, iyr = wyr - cyr, iyi = wyi - cyi, izr = wzr - czr, izi = wzi - czi;
     const double ei = 0.5 * (ixr * ixr + ixi * ixi + iyr * iyr + iyi * iyi + izr * izr + izi * izi);
-    const int fx = kfirst(ix, nx), fy = kfirst(iy, ny), fz = kfirst(iz, nz);
-    const double eq = 2.0 * alpha * alpha * (double)((long)fx * fx + (long)fy * fy + (long)fz * fz) * (ar * ar + ai * ai);
+    const double eq = 0.5 * (qxr * qxr + qxi * qxi + qyr * qyr + qyi * qyi + qzr * qzr + qzi * qzi);
     const double eint = alpha * beta * (br * br + bi * bi);
     const int s = shell_of(k2);
     atomicAdd(&bins[s], ei);
@@ -417,18 +494,23 @@ void launch_mult3(int prec, void* f, int nx, int ny, int nz, const void* mx, con
   if (prec == P_C128) hipLaunchKernelGGL(k_mult3<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, f, nx, ny, nz, mx, my, mz);
   else hipLaunchKernelGGL(k_mult3<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, f, nx, ny, nz, mx, my, mz);
 }
-void launch_diag_fields(int prec, const void* psi, void* f0, void* f1, void* f2, long n, double alpha, double* partial,
-                        unsigned blocks, hipStream_t st) {
-  if (prec == P_C128) hipLaunchKernelGGL(k_diag_fields<double>, dim3(blocks), dim3(256), 0, st, psi, f0, f1, f2, n, alpha, partial);
-  else hipLaunchKernelGGL(k_diag_fields<float>, dim3(blocks), dim3(256), 0, st, psi, f0, f1, f2, n, alpha, partial);
+void launch_diag_fields(int prec, const void* psi, void* f0, void* f1, void* f2, void* f3, long n, double alpha,
+                        double* partial, unsigned blocks, hipStream_t st) {
+  if (prec == P_C128)
+    hipLaunchKernelGGL(k_diag_fields<double>, dim3(blocks), dim3(256), 0, st, psi, f0, f1, f2, f3, n, alpha, partial);
+  else
+    hipLaunchKernelGGL(k_diag_fields<float>, dim3(blocks), dim3(256), 0, st, psi, f0, f1, f2, f3, n, alpha, partial);
 }
-void launch_spectral(int prec, const void* F0, const void* F1, const void* F2, int nx, int ny, int nz, double alpha,
-                     double beta, int nshell, unsigned blocks, long chunk, double* bins, hipStream_t st) {
+void launch_spectral(int prec, const void* F0, const void* F1, const void* F2, const void* F3, int nx, int ny, int nz,
+                     double alpha, double beta, int nshell, unsigned blocks, long chunk, double* bins,
+                     hipStream_t st) {
   const size_t sh = sizeof(double) * 4 * (size_t)nshell;
   if (prec == P_C128)
-    hipLaunchKernelGGL(k_spectral<double>, dim3(blocks), dim3(64), sh, st, F0, F1, F2, nx, ny, nz, alpha, beta, nshell, chunk, bins);
+    hipLaunchKernelGGL(k_spectral<double>, dim3(blocks), dim3(64), sh, st, F0, F1, F2, F3, nx, ny, nz, alpha, beta,
+                       nshell, chunk, bins);
   else
-    hipLaunchKernelGGL(k_spectral<float>, dim3(blocks), dim3(64), sh, st, F0, F1, F2, nx, ny, nz, alpha, beta, nshell, chunk, bins);
+    hipLaunchKernelGGL(k_spectral<float>, dim3(blocks), dim3(64), sh, st, F0, F1, F2, F3, nx, ny, nz, alpha, beta,
+                       nshell, chunk, bins);
 }
 void launch_segsum(const double* in, long len, int nseg, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_segsum, dim3(nseg), dim3(256), 0, st, in, len, out);
@@ -455,6 +537,28 @@ void launch_loss_lambda1(int prec, const void* psi, void* d0, void* d1, void* d2
 void launch_loss_lambda2(int prec, void* lam, const void* e0, const void* e1, const void* e2, long n, hipStream_t st) {
   if (prec == P_C128) hipLaunchKernelGGL(k_loss_lambda2<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, lam, e0, e1, e2, n);
   else hipLaunchKernelGGL(k_loss_lambda2<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, lam, e0, e1, e2, n);
+}
+void launch_argle_explicit(int prec, const void* phi, const void* dx, const void* dy, const void* dz, const void* v,
+                           void* out, long n, double alpha, double beta, hipStream_t st) {
+  if (prec == P_C128)
+    hipLaunchKernelGGL(k_argle_explicit<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, phi, dx, dy, dz, v, out, n, alpha, beta);
+  else
+    hipLaunchKernelGGL(k_argle_explicit<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, phi, dx, dy, dz, v, out, n, alpha, beta);
+}
+void launch_argle_solve(int prec, void* P, const void* Q, int nx, int ny, int nz, double a, double dtau, double inv_n,
+                        hipStream_t st) {
+  const long n = (long)nx * ny * nz;
+  if (prec == P_C128)
+    hipLaunchKernelGGL(k_argle_solve<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, P, Q, nx, ny, nz, a, dtau, inv_n);
+  else
+    hipLaunchKernelGGL(k_argle_solve<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, P, Q, nx, ny, nz, a, dtau, inv_n);
+}
+void launch_argle_energy(int prec, const void* phi, const void* dx, const void* dy, const void* dz, const void* v,
+                         long n, double alpha, double beta, double* partial, unsigned blocks, hipStream_t st) {
+  if (prec == P_C128)
+    hipLaunchKernelGGL(k_argle_energy<double>, dim3(blocks), dim3(256), 0, st, phi, dx, dy, dz, v, n, alpha, beta, partial);
+  else
+    hipLaunchKernelGGL(k_argle_energy<float>, dim3(blocks), dim3(256), 0, st, phi, dx, dy, dz, v, n, alpha, beta, partial);
 }
 void launch_phase_grad(int prec, const void* psi0, const void* lam0, double* out, long n, hipStream_t st) {
   if (prec == P_C128) hipLaunchKernelGGL(k_phase_grad<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, psi0, lam0, out, n);

@@ -558,11 +558,12 @@ gp_status diagnose(gp_plan_s* p, const void* psi, void* work) {
   void* f0 = field(p, work, 0);
   void* f1 = field(p, work, 1);
   void* f2 = field(p, work, 2);
-  launch_diag_fields(p->prec, psi, f0, f1, f2, p->ntot, p->d.alpha, p->field_part, p->field_blocks, p->stream);
+  void* f3 = field(p, work, 3);
+  launch_diag_fields(p->prec, psi, f0, f1, f2, f3, p->ntot, p->d.alpha, p->field_part, p->field_blocks, p->stream);
   if ((st = check_launch(p)) != GP_OK) return st;
-  for (void* f : {f0, f1, f2})
+  for (void* f : {f0, f1, f2, f3})
     if ((st = fwd3_unnorm(p, f)) != GP_OK) return st;
-  launch_spectral(p->prec, f0, f1, f2, p->d.n[0], p->d.n[1], p->d.n[2], p->d.alpha, p->d.beta, p->nshell,
+  launch_spectral(p->prec, f0, f1, f2, f3, p->d.n[0], p->d.n[1], p->d.n[2], p->d.alpha, p->d.beta, p->nshell,
                   p->spec_blocks, p->spec_chunk, p->bins_part, p->stream);
   if ((st = check_launch(p)) != GP_OK) return st;
   // fixed-order reductions of every partial into red = [kin_x, kin_y, kin_z, field[3], spectra[4][nshell]]
@@ -870,6 +871,49 @@ gp_status gp_structure_fn(gp_plan_t* p, const void* psi, void* work, int32_t p_o
   HIPCHK(p, hipMemcpyAsync(p->h_result, p->d_result, (n / 2) * sizeof(double), hipMemcpyDeviceToHost, p->stream));
   HIPCHK(p, hipStreamSynchronize(p->stream));
   memcpy(out, p->h_result, (n / 2) * sizeof(double));
+  return GP_OK;
+}
+
+gp_status gp_argle_step(gp_plan_t* p, void* phi, const void* v, double dtau, int64_t nsteps, void* work) {
+  gp_status st = usable(p);
+  if (st != GP_OK) return st;
+  if (p->is_batch) return fail(GP_ERR_STATE, "batch plan: ARGLE runs on single plans");
+  if (!phi || !v || !work) return fail(GP_ERR_ARG, "null argument");
+  if (!std::isfinite(dtau) || dtau <= 0.0) return fail(GP_ERR_ARG, "dtau must be finite and positive");
+  if (nsteps < 0) return fail(GP_ERR_ARG, "nsteps must be >= 0");
+  void* d0 = field(p, work, 0);
+  void* d1 = field(p, work, 1);
+  void* d2 = field(p, work, 2);
+  void* q = field(p, work, 3);
+  const double a = 0.5 * dtau * p->d.alpha, inv_n = 1.0 / (double)p->ntot;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    if ((st = derivatives(p, phi, work, false)) != GP_OK) return st;
+    launch_argle_explicit(p->prec, phi, d0, d1, d2, v, q, p->ntot, p->d.alpha, p->d.beta, p->stream);
+    if ((st = check_launch(p)) != GP_OK) return st;
+    if ((st = fwd3_unnorm(p, phi)) != GP_OK) return st;
+    if ((st = fwd3_unnorm(p, q)) != GP_OK) return st;
+    launch_argle_solve(p->prec, phi, q, p->d.n[0], p->d.n[1], p->d.n[2], a, dtau, inv_n, p->stream);
+    if ((st = check_launch(p)) != GP_OK) return st;
+    if ((st = inv3_unnorm(p, phi)) != GP_OK) return st;
+  }
+  return GP_OK;
+}
+
+gp_status gp_argle_energy(gp_plan_t* p, const void* phi, const void* v, void* work, double* energy_v) {
+  gp_status st = usable(p);
+  if (st != GP_OK) return st;
+  if (p->is_batch) return fail(GP_ERR_STATE, "batch plan: ARGLE runs on single plans");
+  if (!phi || !v || !work || !energy_v) return fail(GP_ERR_ARG, "null argument");
+  if ((st = derivatives(p, phi, work, false)) != GP_OK) return st;
+  launch_argle_energy(p->prec, phi, field(p, work, 0), field(p, work, 1), field(p, work, 2), v, p->ntot, p->d.alpha,
+                      p->d.beta, p->loss_part, p->field_blocks, p->stream);
+  if ((st = check_launch(p)) != GP_OK) return st;
+  launch_segsum(p->loss_part, p->field_blocks, 1, p->d_result, p->stream);
+  if ((st = check_launch(p)) != GP_OK) return st;
+  HIPCHK(p, hipMemcpyAsync(p->h_result, p->d_result, sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  *energy_v = 2.0 * p->d.alpha * p->h_result[0] / (double)p->ntot;
+  if (!std::isfinite(*energy_v)) return fail(GP_ERR_NONFINITE, "E_v is not finite");
   return GP_OK;
 }
 

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from oracle import gp
-from oracle.fft import kvec
+from oracle.fft import fft3, ifft3, kvec
 import gp_inputs as I
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -172,6 +172,47 @@ def test_quantum_energy_ignores_nyquist_reading():
     assert abs(d["e_q"]) < 1e-24
 
 
+def test_kinetic_plus_quantum_is_the_gradient_energy():
+    """Pointwise, |w|^2 + |q|^2 = 4 alpha^2 |grad psi|^2 (w and q are the imaginary and
+    real parts of 2 alpha conj(psi) grad psi / |psi|), so by Parseval
+    e_kin + e_q = 2 alpha^2 sum_k |k~|^2 |c_k|^2 with the first-derivative k~, for any
+    field without exact zeros -- vortex cores included.  E differs from this sum only
+    through the Nyquist entries of |k|^2."""
+    alpha, beta = 0.3, 2.0
+    for psi in (I.random_field((12, 16, 8), seed=22), I.tg_psi(16, math.sqrt(alpha / beta), 2)):
+        d = gp.diagnostics(psi, alpha, beta)
+        c = fft3(psi)
+        shape = psi.shape
+        fz = gp.first_derivative_k(shape[0])[:, None, None]
+        fy = gp.first_derivative_k(shape[1])[None, :, None]
+        fx = gp.first_derivative_k(shape[2])[None, None, :]
+        grad_e = 2 * alpha ** 2 * float(np.sum((fx * fx + fy * fy + fz * fz) * np.abs(c) ** 2))
+        assert abs(d["e_kin"] + d["e_q"] - grad_e) < 1e-12 * grad_e
+        assert d["e_q"] > 1e-3 * d["e_kin"]
+    # a field with no Nyquist content: E = e_kin + e_q + e_int exactly
+    n = 16
+    z, y, x = _grid3(n)
+    psi = (1 + 0.2 * np.cos(x - 2 * z)) * np.exp(1j * (np.sin(y) + 0.5 * np.cos(x + z))) * np.ones((n, n, n))
+    c = fft3(psi)
+    c[n // 2] = 0; c[:, n // 2] = 0; c[:, :, n // 2] = 0
+    psi = ifft3(c)
+    d = gp.diagnostics(psi, alpha, beta)
+    assert abs(d["e_kin"] + d["e_q"] + d["e_int"] - d["energy"]) < 1e-12 * d["energy"]
+
+
+def test_quantum_field_is_grad_amplitude():
+    """q = 2 alpha grad |psi| for a smooth field with a band-limited phase and amplitude
+    (checked against the analytic gradient, up to the spectral truncation of psi)."""
+    n, alpha = 32, 0.25
+    z, y, x = _grid3(n)
+    amp = 1.0 + 0.3 * np.sin(y) * np.cos(z)
+    psi = amp * np.exp(1j * 0.2 * np.cos(x))
+    q = gp.quantum_q(psi, alpha)
+    exact = [-0.3 * 2 * alpha * np.sin(y) * np.sin(z), 0.3 * 2 * alpha * np.cos(y) * np.cos(z) + 0 * x, 0 * x + 0 * y * z]
+    for j in range(3):
+        assert np.abs(q[j] - exact[j]).max() < 1e-10
+
+
 def test_helmholtz_pure_fields():
     n = 12
     z, y, x = _grid3(n)
@@ -199,7 +240,11 @@ def test_srp_initial_state_diagnostics():
     theta = I.srp_fourier_theta(32, 4, 0)
     psi = np.exp(1j * theta)
     d = gp.diagnostics(psi, 1.0, 1.0)
-    assert d["e_int"] < 1e-28 and abs(d["e_q"]) < 1e-26
+    # rho = 1 exactly; q = 2 alpha Re(conj(psi) grad psi) vanishes up to the spectral
+    # truncation of exp(i theta) (gone at 64^3)
+    assert d["e_int"] < 1e-28 and abs(d["e_q"]) < 1e-4 * d["e_kin"]
+    d64 = gp.diagnostics(np.exp(1j * I.srp_fourier_theta(64, 4, 0)), 1.0, 1.0)
+    assert abs(d64["e_q"]) < 1e-12 * d64["e_kin"]
     assert d["e_kin_i"] < 1e-3 * d["e_kin"]
     assert abs(d["e_kin_i"] + d["e_kin_c"] - d["e_kin"]) < 1e-13 * d["e_kin"]
     assert abs(d["energy"] - d["e_kin"]) < 1e-2 * d["e_kin"]
