@@ -18,6 +18,12 @@ Initial conditions follow the paper's "Initial data preparation" section:
   psi_e (eq. psie, tanh argument read as r / (sqrt(2) xi)), the product of
   four shifted copies (eq. psi4) raised to [1/(2 pi alpha)] (eq. psitot3d),
   evaluated directly on [0, 2 pi)^3; no imaginary-time relaxation.
+* ``abc_velocity`` / ``abc_psi`` -- the sum of two Arnold-Beltrami-Childress
+  flows (eq. ABC with k = 1 and k = 2; the paper's large-scale spectrum has
+  exactly these two modes) and the phase-only ansatz psi_ABC^(1) psi_ABC^(2)
+  (eq. ABCphi0, eq. ABCphi): per flow and coefficient a phase that is linear in
+  the two other coordinates with integer slopes [A sin(kx)/(2 alpha)],
+  [A cos(kx)/(2 alpha)] (nearest integer, numpy rint), so psi is periodic.
 * ``rvr_psi`` -- random vortex-ring pairs: Pade profile (eq. Pade and its
   coefficients), ring phase atan2(z~, r - R), pair psi_VR(z - d/2) conj
   psi_VR(z + d/2), six mirror-conjugate images (eq. psiRP), random translation
@@ -31,7 +37,8 @@ import math
 import numpy as np
 
 __all__ = [
-    "grid", "srp_fourier_theta", "srp_mode_count", "tg_psi", "pade_f",
+    "grid", "srp_fourier_theta", "srp_mode_count", "tg_psi", "tg_velocity", "abc_velocity", "abc_psi",
+    "ABC_COEFFS", "pade_f",
     "PADE_A1", "PADE_A2", "PADE_B1", "rvr_psi", "rvr_draws", "random_field",
     "random_real", "alpha_beta_from_xi", "alpha_beta_table1", "WORKLOADS",
 ]
@@ -87,6 +94,38 @@ def tg_velocity(n: int):
     vz = np.zeros((n, n, n))
     return [vz, np.ascontiguousarray(np.broadcast_to(vy, (n, n, n))),
             np.ascontiguousarray(np.broadcast_to(vx, (n, n, n)))]
+
+
+ABC_COEFFS = (0.9 / math.sqrt(3.0), 1.0 / math.sqrt(3.0), 1.1 / math.sqrt(3.0))   # (A, B, C)
+
+
+def abc_velocity(n: int, coeffs=ABC_COEFFS, ks=(1, 2)):
+    """v_ABC = sum over k in ks of the ABC flow of wavenumber k (eq. ABC), as the
+    components [v_z, v_y, v_x] (FP64, each shaped [z][y][x])."""
+    A, B, C = coeffs
+    x = grid(n)
+    X, Y, Z = x[None, None, :], x[None, :, None], x[:, None, None]
+    vx = sum(B * np.cos(k * Y) + C * np.sin(k * Z) for k in ks)
+    vy = sum(C * np.cos(k * Z) + A * np.sin(k * X) for k in ks)
+    vz = sum(A * np.cos(k * X) + B * np.sin(k * Y) for k in ks)
+    full = (n, n, n)
+    return [np.ascontiguousarray(np.broadcast_to(c, full)) for c in (vz, vy, vx)]
+
+
+def abc_psi(n: int, alpha: float, coeffs=ABC_COEFFS, ks=(1, 2)) -> np.ndarray:
+    """Phase-only ABC ansatz prod_k psi_{A,k}^{x,y,z} psi_{B,k}^{y,z,x} psi_{C,k}^{z,x,y}
+    (eq. ABCphi0, eq. ABCphi): psi_{A,k}^{x,y,z} = exp(i [A sin(kx)/(2 alpha)] y
+    + i [A cos(kx)/(2 alpha)] z), the others by cyclic permutation of (x, y, z)."""
+    A, B, C = coeffs
+    x = grid(n)
+    X, Y, Z = x[None, None, :], x[None, :, None], x[:, None, None]
+    h = 1.0 / (2.0 * alpha)
+    theta = np.zeros((n, n, n))
+    for k in ks:
+        theta = theta + np.rint(A * h * np.sin(k * X)) * Y + np.rint(A * h * np.cos(k * X)) * Z
+        theta = theta + np.rint(B * h * np.sin(k * Y)) * Z + np.rint(B * h * np.cos(k * Y)) * X
+        theta = theta + np.rint(C * h * np.sin(k * Z)) * X + np.rint(C * h * np.cos(k * Z)) * Y
+    return np.exp(1j * theta)
 
 
 def tg_psi(n: int, xi: float, exponent: int) -> np.ndarray:
@@ -225,6 +264,10 @@ WORKLOADS = {
     # xi = sqrt(alpha/beta)
     "tg128_argle": dict(n=128, prec=("c128",), alpha=0.05, beta=40.0, dtau=1.25e-2, steps=4800,
                         ic=("tg", dict(xi=math.sqrt(0.05 / 40.0), exponent=3)), velocity="tg"),
+    # ABC preparation, run ABC_aIT of the paper's ABC parameter table: 128^3,
+    # alpha = 0.05, beta = 40 (parameter-table rule), dtau = 4e-3, tau_f = 30
+    "abc128_argle": dict(n=128, prec=("c128",), alpha=0.05, beta=40.0, dtau=4e-3, steps=7500,
+                         ic=("abc", {}), velocity="abc"),
     "ens48": dict(runs=[dict(n=64, alpha=0.1, beta=20.0, seed=100 + i) for i in range(32)]
                   + [dict(n=96, alpha=6.4 / 96, beta=30.0, seed=132 + i) for i in range(16)],
                   prec=("c64",), dt=1e-3, steps=300, K=4, diag_every=50),

@@ -193,6 +193,27 @@ GP_API gp_status gp_argle_step(gp_plan_t* p, void* phi, const void* v, double dt
  * gp_argle_step; energy_v: host out.  Synchronizes. */
 GP_API gp_status gp_argle_energy(gp_plan_t* p, const void* phi, const void* v, void* work, double* energy_v);
 
+/* Outcome of gp_argle_run (values of the last check). */
+typedef struct {
+  int64_t steps;       /* steps taken */
+  double crit_sup;     /* ||phi^{n+1} - phi^n||_inf / dtau            (eq. crit1) */
+  double crit_energy;  /* |E_v^{n+1} - E_v^n| / (dtau E_v^n)         (eq. crit2) */
+  double e_v;          /* E_v of the returned field                            */
+  int32_t converged;   /* 1 if a check met crit_sup <= eps                       */
+} gp_argle_report;
+
+/* The ARGLE procedure with its stopping rule (section on computing stationary
+ * solutions): steps of gp_argle_step until eq. crit1 holds or max_steps steps
+ * are done.  The criteria are evaluated on every check_every-th step and on the
+ * last step (a check adds one E_v evaluation before and after the step and a
+ * copy of phi^n into the fifth workspace state); the run stops at the first
+ * check with crit_sup <= eps.  eps <= 0 runs max_steps steps and reports the
+ * criteria of the last one (the paper's fixed tau_f runs).  max_steps = 0:
+ * crit_sup = crit_energy = NaN and e_v = E_v(phi).  work: dev, gp_work_bytes
+ * (all five states used).  report: host out.  Synchronizes at every check. */
+GP_API gp_status gp_argle_run(gp_plan_t* p, void* phi, const void* v, double dtau, int64_t max_steps,
+                              int64_t check_every, double eps, void* work, gp_argle_report* report);
+
 /* Ensemble: advance run i's state psis[i] (host array of dev pointers) by nsteps.
  * The first call for a given set of pointers and nsteps records a HIP graph;
  * later identical calls replay it. */

@@ -37,7 +37,7 @@ import numpy as np
 from .fft import fft3, ifft3
 from .gp import gradient, ksq
 
-__all__ = ["explicit_part", "argle_step", "argle", "energy_v", "crit_sup", "crit_energy"]
+__all__ = ["explicit_part", "argle_step", "argle", "energy_v", "crit_sup", "crit_energy", "argle_run"]
 
 
 def explicit_part(phi, v, alpha, beta, engine=None):
@@ -87,3 +87,28 @@ def crit_sup(phi_new, phi_old, dtau) -> float:
 def crit_energy(e_new, e_old, dtau) -> float:
     """Left side of eq. crit2: |E_v^{n+1} - E_v^n| / (dtau E_v^n)."""
     return abs(e_new - e_old) / (dtau * e_old)
+
+
+def argle_run(phi, v, alpha, beta, dtau, max_steps, check_every, eps, engine=None):
+    """The ARGLE procedure with its stopping rule (section on stationary solutions):
+    step until eq. crit1 holds or max_steps steps are done.  The criteria are
+    evaluated on every check_every-th step and on the last one (a check costs one
+    extra E_v evaluation and a saved copy of phi^n); the run stops at the first
+    check whose crit_sup <= eps.  Returns (phi, steps, crit_sup, crit_energy, e_v,
+    converged) with the values of the last check; crit_energy is eq. crit2, the
+    fallback measure when crit1 is not reached.  With max_steps = 0 nothing is
+    checked: crit_sup = crit_energy = nan, e_v = E_v(phi)."""
+    phi = np.asarray(phi, dtype=np.complex128)
+    steps, cs, ce = 0, float("nan"), float("nan")
+    while steps < max_steps:
+        check = (steps + 1) % check_every == 0 or steps + 1 == max_steps
+        if check:
+            old, e_old = phi, energy_v(phi, v, alpha, beta, engine)
+        phi = argle_step(phi, v, alpha, beta, dtau, engine)
+        steps += 1
+        if check:
+            cs = crit_sup(phi, old, dtau)
+            ce = crit_energy(energy_v(phi, v, alpha, beta, engine), e_old, dtau)
+            if cs <= eps:
+                return phi, steps, cs, ce, energy_v(phi, v, alpha, beta, engine), True
+    return phi, steps, cs, ce, energy_v(phi, v, alpha, beta, engine), False

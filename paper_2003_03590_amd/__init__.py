@@ -14,7 +14,7 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import GPError, GP_C128, GP_C64, gp_desc, gp_energy
+from ._lib import GPError, GP_C128, GP_C64, gp_argle_report, gp_desc, gp_energy
 
 __all__ = ["lib", "Plan", "BatchPlan", "evolve", "ekin_i_shells", "GPError", "GP_C128", "GP_C64"]
 
@@ -186,6 +186,20 @@ class Plan:
         _check(lib().gp_argle_energy(self._h, self._field(phi, "phi"), C.c_void_p(v.data_ptr()),
                                      C.c_void_p(_ptr(self.work())), C.byref(out)))
         return out.value
+
+    def argle_run(self, phi, v, dtau: float, max_steps: int, check_every: int = 100, eps: float = 0.0) -> dict:
+        """The ARGLE procedure with its stopping rule: steps until
+        ||phi^{n+1} - phi^n||_inf / dtau <= eps at a check (every check_every steps
+        and the last step) or max_steps steps.  Returns steps, crit_sup, crit_energy,
+        e_v and converged of the last check."""
+        v = self._velocity(v)
+        r = gp_argle_report()
+        _check(lib().gp_argle_run(self._h, self._field(phi, "phi"), C.c_void_p(v.data_ptr()), float(dtau),
+                                  int(max_steps), int(check_every), float(eps), C.c_void_p(_ptr(self.work())),
+                                  C.byref(r)))
+        out = r.as_dict()
+        out["converged"] = bool(out["converged"])
+        return out
 
     def spectra(self, psi):
         out = np.zeros((4, self.nshell), dtype=np.float64)

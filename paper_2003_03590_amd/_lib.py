@@ -30,6 +30,14 @@ class gp_energy(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class gp_argle_report(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("crit_sup", C.c_double), ("crit_energy", C.c_double), ("e_v", C.c_double),
+                ("converged", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 P = C.c_void_p
 PP = C.POINTER(C.c_void_p)
 ST = C.c_int
@@ -57,6 +65,7 @@ SIGNATURES = {
     "gp_phase_grad": (ST, [P, P, P, P]),
     "gp_argle_step": (ST, [P, P, P, C.c_double, C.c_int64, P]),
     "gp_argle_energy": (ST, [P, P, P, P, C.POINTER(C.c_double)]),
+    "gp_argle_run": (ST, [P, P, P, C.c_double, C.c_int64, C.c_int64, C.c_double, P, C.POINTER(gp_argle_report)]),
     "gp_step_n_batch": (ST, [P, PP, C.c_int64]),
     "gp_energies_batch": (ST, [P, PP, P, C.POINTER(C.c_double)]),
     "gp_last_error": (C.c_char_p, []),

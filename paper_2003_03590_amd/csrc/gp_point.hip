@@ -167,6 +167,45 @@ __global__ __launch_bounds__(256) void k_argle_energy(const void* phi, const voi
   if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
+// max |a - b|^2 over the field (sup norm of an update, eq. crit1): per-block maxima
+// in partial[block]; the maximum is exact, so the result does not depend on order.
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ __forceinline__ double block_max256(double v, double* sh) {
+  v = wave_max(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+  return r;
+}
+
+template <class Real>
+__global__ __launch_bounds__(256) void k_sup_diff2(const void* a, const void* b, long n,
+                                                   double* __restrict__ partial) {
+  __shared__ double sh[4];
+  double m = 0.0;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+    const cplx<Real> x = ldc<Real>(a, i), y = ldc<Real>(b, i);
+    const double dr = (double)x.x - (double)y.x, di = (double)x.y - (double)y.y;
+    m = fmax(m, dr * dr + di * di);
+  }
+  const double r = block_max256(m, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+__global__ __launch_bounds__(256) void k_segmax(const double* __restrict__ in, long len, double* __restrict__ out) {
+  __shared__ double sh[4];
+  double m = 0.0;
+  for (long b = threadIdx.x; b < len; b += 256) m = fmax(m, in[b]);
+  const double r = block_max256(m, sh);
+  if (threadIdx.x == 0) out[0] = r;
+}
+
 // ----------------------------------------------------------------- diagnostics
 // In: psi and its spectral derivatives d0 = d/dx, d1 = d/dy, d2 = d/dz (in f0, f1, f2).
 // Out (in place): f0 = w_x + i w_y, f1 = w_z + i q_x, f2 = q_y + i q_z, f3 = (|psi|^2 - 1) + 0i,
@@ -511,6 +550,12 @@ void launch_spectral(int prec, const void* F0, const void* F1, const void* F2, c
   else
     hipLaunchKernelGGL(k_spectral<float>, dim3(blocks), dim3(64), sh, st, F0, F1, F2, F3, nx, ny, nz, alpha, beta,
                        nshell, chunk, bins);
+}
+void launch_sup_diff2(int prec, const void* a, const void* b, long n, double* partial, unsigned blocks, double* out,
+                      hipStream_t st) {
+  if (prec == P_C128) hipLaunchKernelGGL(k_sup_diff2<double>, dim3(blocks), dim3(256), 0, st, a, b, n, partial);
+  else hipLaunchKernelGGL(k_sup_diff2<float>, dim3(blocks), dim3(256), 0, st, a, b, n, partial);
+  hipLaunchKernelGGL(k_segmax, dim3(1), dim3(256), 0, st, partial, (long)blocks, out);
 }
 void launch_segsum(const double* in, long len, int nseg, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_segsum, dim3(nseg), dim3(256), 0, st, in, len, out);

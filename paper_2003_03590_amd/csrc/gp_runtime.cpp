@@ -874,13 +874,9 @@ gp_status gp_structure_fn(gp_plan_t* p, const void* psi, void* work, int32_t p_o
   return GP_OK;
 }
 
-gp_status gp_argle_step(gp_plan_t* p, void* phi, const void* v, double dtau, int64_t nsteps, void* work) {
-  gp_status st = usable(p);
-  if (st != GP_OK) return st;
-  if (p->is_batch) return fail(GP_ERR_STATE, "batch plan: ARGLE runs on single plans");
-  if (!phi || !v || !work) return fail(GP_ERR_ARG, "null argument");
-  if (!std::isfinite(dtau) || dtau <= 0.0) return fail(GP_ERR_ARG, "dtau must be finite and positive");
-  if (nsteps < 0) return fail(GP_ERR_ARG, "nsteps must be >= 0");
+// nsteps steps of the semi-implicit backward Euler scheme; work slots 0..3
+static gp_status argle_steps(gp_plan_s* p, void* phi, const void* v, double dtau, int64_t nsteps, void* work) {
+  gp_status st;
   void* d0 = field(p, work, 0);
   void* d1 = field(p, work, 1);
   void* d2 = field(p, work, 2);
@@ -899,11 +895,9 @@ gp_status gp_argle_step(gp_plan_t* p, void* phi, const void* v, double dtau, int
   return GP_OK;
 }
 
-gp_status gp_argle_energy(gp_plan_t* p, const void* phi, const void* v, void* work, double* energy_v) {
-  gp_status st = usable(p);
-  if (st != GP_OK) return st;
-  if (p->is_batch) return fail(GP_ERR_STATE, "batch plan: ARGLE runs on single plans");
-  if (!phi || !v || !work || !energy_v) return fail(GP_ERR_ARG, "null argument");
+// E_v (synchronizes); work slots 0..2
+static gp_status argle_energy(gp_plan_s* p, const void* phi, const void* v, void* work, double* energy_v) {
+  gp_status st;
   if ((st = derivatives(p, phi, work, false)) != GP_OK) return st;
   launch_argle_energy(p->prec, phi, field(p, work, 0), field(p, work, 1), field(p, work, 2), v, p->ntot, p->d.alpha,
                       p->d.beta, p->loss_part, p->field_blocks, p->stream);
@@ -914,6 +908,68 @@ gp_status gp_argle_energy(gp_plan_t* p, const void* phi, const void* v, void* wo
   HIPCHK(p, hipStreamSynchronize(p->stream));
   *energy_v = 2.0 * p->d.alpha * p->h_result[0] / (double)p->ntot;
   if (!std::isfinite(*energy_v)) return fail(GP_ERR_NONFINITE, "E_v is not finite");
+  return GP_OK;
+}
+
+static gp_status argle_args(gp_plan_s* p, const void* phi, const void* v, const void* work) {
+  gp_status st = usable(p);
+  if (st != GP_OK) return st;
+  if (p->is_batch) return fail(GP_ERR_STATE, "batch plan: ARGLE runs on single plans");
+  if (!phi || !v || !work) return fail(GP_ERR_ARG, "null argument");
+  return GP_OK;
+}
+
+gp_status gp_argle_step(gp_plan_t* p, void* phi, const void* v, double dtau, int64_t nsteps, void* work) {
+  gp_status st = argle_args(p, phi, v, work);
+  if (st != GP_OK) return st;
+  if (!std::isfinite(dtau) || dtau <= 0.0) return fail(GP_ERR_ARG, "dtau must be finite and positive");
+  if (nsteps < 0) return fail(GP_ERR_ARG, "nsteps must be >= 0");
+  return argle_steps(p, phi, v, dtau, nsteps, work);
+}
+
+gp_status gp_argle_energy(gp_plan_t* p, const void* phi, const void* v, void* work, double* energy_v) {
+  gp_status st = argle_args(p, phi, v, work);
+  if (st != GP_OK) return st;
+  if (!energy_v) return fail(GP_ERR_ARG, "null argument");
+  return argle_energy(p, phi, v, work, energy_v);
+}
+
+gp_status gp_argle_run(gp_plan_t* p, void* phi, const void* v, double dtau, int64_t max_steps, int64_t check_every,
+                       double eps, void* work, gp_argle_report* report) {
+  gp_status st = argle_args(p, phi, v, work);
+  if (st != GP_OK) return st;
+  if (!report) return fail(GP_ERR_ARG, "null argument");
+  if (!std::isfinite(dtau) || dtau <= 0.0) return fail(GP_ERR_ARG, "dtau must be finite and positive");
+  if (max_steps < 0) return fail(GP_ERR_ARG, "max_steps must be >= 0");
+  if (check_every < 1) return fail(GP_ERR_ARG, "check_every must be >= 1");
+  if (std::isnan(eps)) return fail(GP_ERR_ARG, "eps is NaN");
+  gp_argle_report r{0, std::nan(""), std::nan(""), 0.0, 0};
+  void* old = field(p, work, 4);
+  const size_t bytes = (size_t)p->ntot * p->S;
+  bool have_e = false;
+  while (r.steps < max_steps) {
+    const int64_t next = std::min<int64_t>((r.steps / check_every + 1) * check_every, max_steps);   // check step
+    if ((st = argle_steps(p, phi, v, dtau, next - r.steps - 1, work)) != GP_OK) return st;
+    double e_old, e_new, sup2;
+    if ((st = argle_energy(p, phi, v, work, &e_old)) != GP_OK) return st;
+    HIPCHK(p, hipMemcpyAsync(old, phi, bytes, hipMemcpyDeviceToDevice, p->stream));
+    if ((st = argle_steps(p, phi, v, dtau, 1, work)) != GP_OK) return st;
+    launch_sup_diff2(p->prec, phi, old, p->ntot, p->field_part, p->field_blocks, p->d_result, p->stream);
+    if ((st = check_launch(p)) != GP_OK) return st;
+    HIPCHK(p, hipMemcpyAsync(p->h_result, p->d_result, sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(p, hipStreamSynchronize(p->stream));
+    sup2 = p->h_result[0];
+    if ((st = argle_energy(p, phi, v, work, &e_new)) != GP_OK) return st;
+    r.steps = next;
+    r.crit_sup = std::sqrt(sup2) / dtau;
+    r.crit_energy = std::fabs(e_new - e_old) / (dtau * e_old);
+    r.e_v = e_new;
+    have_e = true;
+    if (!std::isfinite(r.crit_sup)) return fail(GP_ERR_NONFINITE, "ARGLE update is not finite at step %lld", (long long)next);
+    if (r.crit_sup <= eps) { r.converged = 1; break; }
+  }
+  if (!have_e && (st = argle_energy(p, phi, v, work, &r.e_v)) != GP_OK) return st;
+  *report = r;
   return GP_OK;
 }
 

@@ -152,3 +152,123 @@ def test_golden_table_is_consistent():
         for j in range(5):
             rel = abs(r[3 + j] - a[3 + j]) / a[3 + j]
             assert abs(rel - err[j]) < 0.02 * err[j] + 2e-5, (name, j, rel, err[j])
+
+
+def test_stopping_rule_matches_the_scalar_recursion():
+    """Uniform phi = c, v = 0: every step is the scalar map c <- c + dtau beta (1 - |c|^2) c
+    (k = 0 only), so eq. crit1 at step n is |c_{n+1} - c_n| / dtau and eq. crit2 follows
+    from E_v = alpha beta (|c|^2 - 1)^2.  The run must stop at the first check where the
+    scalar recursion's crit1 <= eps, with the same criteria."""
+    n, alpha, beta, dtau, eps = 6, 0.3, 2.0, 0.05, 1e-3
+    c0 = 0.4 * np.exp(-0.3j)
+    v = _uniform_v(n, 0.0, 0.0, 0.0)
+    for every in (1, 7):
+        c, k, want = c0, 0, None
+        while want is None:
+            cn = c + dtau * beta * (1 - abs(c) ** 2) * c
+            k += 1
+            if k % every == 0:
+                cs = abs(cn - c) / dtau
+                e_old, e_new = alpha * beta * (abs(c) ** 2 - 1) ** 2, alpha * beta * (abs(cn) ** 2 - 1) ** 2
+                if cs <= eps:
+                    want = (k, cs, abs(e_new - e_old) / (dtau * e_old), e_new)
+            c = cn
+        phi, steps, cs, ce, ev, conv = A.argle_run(np.full((n, n, n), c0), v, alpha, beta, dtau, 10000, every, eps)
+        assert conv and steps == want[0], (every, steps, want)
+        assert abs(cs - want[1]) < 1e-9 * want[1] and abs(ce - want[2]) < 1e-9 * want[2]
+        assert abs(ev - want[3]) < 1e-9 * want[3] and abs(phi[0, 0, 0] - c) < 1e-13
+    # a cap below the convergence step: not converged, criteria of the last step
+    phi, steps, cs, ce, ev, conv = A.argle_run(np.full((n, n, n), c0), v, alpha, beta, dtau, 5, 3, eps)
+    assert not conv and steps == 5 and cs > eps
+    c = c0
+    for _ in range(4):
+        c = c + dtau * beta * (1 - abs(c) ** 2) * c
+    assert abs(cs - beta * (1 - abs(c) ** 2) * abs(c)) < 1e-12
+
+
+def _rows(name):
+    import os
+    rows = {}
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", name)):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        rows[f[0]] = [float(v) for v in f[1:]]
+    return rows
+
+
+def test_printed_energies_support_the_pointwise_quantum_reading():
+    """E_kin + E_q = 2 alpha^2 sum |k~|^2 |c_k|^2 holds exactly only with E_q taken
+    pointwise from psi's derivatives, so E = E_kin^i + E_kin^c + E_q + E_int up to the
+    Nyquist entries.  The paper's tables agree: the four energies of TG_aIT, TG_bIT and
+    TG_cIT add up to the E(0) of the runs TG_a, TG_b, TG_c they start (1e-6 relative).
+    (The TG_d row of the conservation table does not match TG_dIT; not used.)"""
+    prep = _rows("tg_argle_energies.txt")
+    cons = _rows("tg_conservation.txt")
+    for it, run in (("TG_aIT", "TG_a"), ("TG_bIT", "TG_b"), ("TG_cIT", "TG_c")):
+        total = sum(prep[it][3:7])
+        e0 = cons[run][8]
+        assert abs(total - e0) < 1e-6 * e0, (it, total, e0)
+        assert prep[it][0] == cons[run][0] and prep[it][1] == cons[run][1]
+    # delta(E) is a maximum over the run, so it is at least the end-point change
+    for run, r in cons.items():
+        assert r[10] >= abs(r[9] - r[8]) / r[8] - 1e-6, run      # 7 printed digits
+        assert r[5] == r[6] and r[7] == 0.0
+
+
+def test_abc_velocity_is_the_classical_helical_flow():
+    """v_ABC (eq. ABC, k = 1 and 2) is divergence free and Beltrami per wavenumber
+    (curl v^(k) = k v^(k)); its kinetic energy is A^2 + B^2 + C^2 = 1.0067 (the paper:
+    E_kin^i close to 1) and its helicity <v . curl v> = 3 (A^2 + B^2 + C^2) = 3.02 (the
+    paper's classical value 3)."""
+    n = 16
+    k = kvec(n)
+    def d(f, axis):
+        shape = [1, 1, 1]; shape[axis] = n
+        return np.real(np.fft.ifftn(1j * k.reshape(shape) * np.fft.fftn(f)))
+    def curl(v):
+        vz, vy, vx = v
+        return [d(vy, 2) - d(vx, 1), d(vx, 0) - d(vz, 2), d(vz, 1) - d(vy, 0)]   # [w_z, w_y, w_x]
+    A, B, C = I.ABC_COEFFS
+    s2 = A * A + B * B + C * C
+    for kk in (1, 2):
+        v = I.abc_velocity(n, ks=(kk,))
+        w = curl(v)
+        assert max(np.abs(w[j] - kk * v[j]).max() for j in range(3)) < 1e-12
+    v = I.abc_velocity(n)
+    vz, vy, vx = v
+    assert np.abs(d(vx, 2) + d(vy, 1) + d(vz, 0)).max() < 1e-12
+    assert abs(0.5 * np.mean(vx ** 2 + vy ** 2 + vz ** 2) - s2) < 1e-12
+    w = curl(v)
+    assert abs(np.mean(sum(v[j] * w[j] for j in range(3))) - 3 * s2) < 1e-12
+
+
+def test_abc_ansatz_is_a_periodic_phase_with_the_flow_velocity():
+    """psi_ABC (eq. ABCphi0, eq. ABCphi) has |psi| = 1; its phase is linear in the
+    transverse coordinates with integer slopes, so each factor is periodic; where the
+    slopes are locally constant its superfluid velocity 2 alpha grad(theta) is the
+    rounded ABC velocity (within alpha of v_ABC per flow and coefficient)."""
+    n, alpha = 32, 0.4              # few slope changes per period at this alpha
+    psi = I.abc_psi(n, alpha)
+    assert np.abs(np.abs(psi) - 1).max() < 1e-13
+    A, B, C = I.ABC_COEFFS
+    x = I.grid(n)
+    for coef in (A, B, C):
+        for k in (1, 2):
+            m = np.rint(coef / (2 * alpha) * np.sin(k * x))
+            assert np.all(np.abs(2 * alpha * m - coef * np.sin(k * x)) <= alpha + 1e-15)
+    # phase increment along y over one cell, where none of the integer slopes that
+    # depend on y ([B sin(ky)/(2 alpha)], [B cos(ky)/(2 alpha)]) changes: it is
+    # dy times the y slope sum_k [A sin(kx)/(2 alpha)] + [C cos(kz)/(2 alpha)]
+    dy = 2 * np.pi / n
+    inc = np.roll(psi, -1, axis=1) * np.conj(psi)
+    X, Y, Z = x[None, None, :], x[None, :, None], x[:, None, None]
+    slope = sum(np.rint(A * np.sin(k * X) / (2 * alpha)) + np.rint(C * np.cos(k * Z) / (2 * alpha)) for k in (1, 2))
+    steady = np.ones((1, n, 1), dtype=bool)
+    for k in (1, 2):
+        for f in (np.sin, np.cos):
+            m = np.rint(B * f(k * Y) / (2 * alpha))
+            steady &= (np.roll(m, -1, axis=1) == m)
+    assert steady.sum() >= 4
+    err = np.abs(inc - np.exp(1j * slope * dy)) * steady
+    assert err.max() < 1e-10
