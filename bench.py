@@ -168,6 +168,48 @@ def large_form(gp, torch, I, steps=5):
     return out
 
 
+ARGLE_BYTES_PER_POINT = 33.5    # x S bytes per grid point and ARGLE step (see argle_form)
+
+
+def argle_form(gp, torch, I, steps=200, warmup=20):
+    """Imaginary-time (ARGLE) preparation at 256^3 complex128 in the configuration
+    of the grid-convergence run TG_h (alpha = 0.05, beta = 40, dtau = 6.25e-3, Taylor-
+    Green ansatz and flow): `steps` steps timed with HIP events on the plan's stream.
+    Algorithmic bytes per step, in units of S = 16 bytes per point: three derivative
+    passes (read phi, write d_j: 6), the explicit part (read phi, d_x, d_y, d_z and the
+    three real velocity planes, write n: 6.5), forward 3-D transforms of phi and n
+    (3 passes each, 12), the diagonal solve (read both, write phi: 3) and the inverse
+    3-D transform (6): 33.5 S."""
+    import numpy as np
+    n, alpha, beta, dtau = 256, 0.05, 40.0, 6.25e-3
+    plan = gp.Plan(n, alpha, beta, 1e-3, "c128")
+    expo = int(math.floor(1.0 / (2 * math.pi * alpha)))
+    phi = torch.from_numpy(I.tg_psi(n, math.sqrt(alpha / beta), expo)).to("cuda").contiguous()
+    vz, vy, vx = I.tg_velocity(n)
+    v = torch.from_numpy(np.stack([vx, vy, vz])).to("cuda").contiguous()
+    plan.argle_step(phi, v, dtau, warmup)
+    st = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(st)
+    plan.argle_step(phi, v, dtau, steps)
+    b.record(st)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    per_step = ARGLE_BYTES_PER_POINT * 16.0 * float(n) ** 3
+    gbs = per_step / (ms / 1e3) / 1e9
+    out = {"workload": "TG_h preparation: 256^3 complex128, alpha = 0.05, beta = 40, dtau = 6.25e-3, "
+                       "Taylor-Green ansatz and flow",
+           "steps": steps, "ms_per_step": ms, "value": float(n) ** 3 / (ms / 1e3), "unit": "grid-point.steps/s",
+           "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": gbs / HBM_PEAK_GBS, "per_step_bytes": per_step, "traffic": None,
+                        "kernel": "whole ARGLE step (axis passes, explicit part, diagonal solve)"}}
+    plan.close()
+    del phi, v
+    torch.cuda.empty_cache()
+    return out
+
+
 def passes_mode(gp, torch, spec, reps, tune=False, variants=None):
     """Each axis pass (propagator sub-step S(s, L_j)) `reps` times on a random
     N^3 field, then `reps` device copies of the same bytes (calibration of the
@@ -237,6 +279,9 @@ def main(argv=None):
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the 1024^3 complex64 HBM-bound form")
+    ap.add_argument("--no-argle", action="store_true", help="skip the 256^3 imaginary-time preparation form")
+    ap.add_argument("--argle", action="store_true",
+                    help="profiling mode: time only the 256^3 imaginary-time preparation, print its JSON, exit")
     ap.add_argument("--passes", default=None, metavar="N:PREC",
                     help="profiling mode: time each axis pass alone on an N^3 field (PREC c128|c64) "
                          "and one device copy of the same bytes, then exit")
@@ -258,6 +303,9 @@ def main(argv=None):
 
     if a.passes:
         return passes_mode(gp, torch, a.passes, a.reps, tune=a.tune, variants=a.variants)
+    if a.argle:
+        print(json.dumps(argle_form(gp, torch, I)))
+        return 0
 
     w = I.WORKLOADS[WORKLOAD]
     n = w["n"]
@@ -315,6 +363,8 @@ def main(argv=None):
         res["ensemble"] = ensemble_form(gp, torch, I)
     if not a.no_large:
         res["large_1024_c64"] = large_form(gp, torch, I)
+    if not a.no_argle:
+        res["argle_256"] = argle_form(gp, torch, I)
     if not a.no_cpu_baseline:
         res["cpu_baseline"] = oracle_sample(psi0, w)
     print(json.dumps(res))

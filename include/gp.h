@@ -182,7 +182,7 @@ GP_API gp_status gp_phase_grad(gp_plan_t* p, const void* psi0, const void* lam0,
  * alpha, beta from the plan (its dt is not used).  phi: dev, in/out, N^3 complex.
  * v: dev, three real fields v_x, v_y, v_z of the plan's real precision (FP64 for
  * GP_C128, FP32 for GP_C64), each N^3 in the [z][y][x] order of phi.  dtau > 0,
- * nsteps >= 0.  work: dev, gp_work_bytes (four states used).  |k|^2 of the
+ * nsteps >= 0.  work: dev, gp_work_bytes (three states used).  |k|^2 of the
  * Laplacian uses N^2/4 at the Nyquist index; first derivatives use 0 there.
  * Asynchronous on the plan's stream.  Not for batch plans (GP_ERR_STATE). */
 GP_API gp_status gp_argle_step(gp_plan_t* p, void* phi, const void* v, double dtau, int64_t nsteps, void* work);

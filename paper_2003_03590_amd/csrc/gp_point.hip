@@ -103,39 +103,40 @@ __global__ void k_mult3(void* f, int nx, int ny, int nz, const void* mx, const v
 // (eq. semi-backward-Euler).  v holds three real fields v_x, v_y, v_z of the working
 // precision; d_x, d_y, d_z are the spectral first derivatives of phi.
 
-// explicit part: n = -i v.grad phi + (beta - |v|^2/(4 alpha) - beta |phi|^2) phi
+// explicit part: n = -i v.grad phi + (beta - |v|^2/(4 alpha) - beta |phi|^2) phi.
+// One point per thread (n <= 2^30, so 32-bit indices), q4a = 1/(4 alpha).
 template <class Real>
 __global__ __launch_bounds__(256) void k_argle_explicit(const void* phi, const void* dx, const void* dy,
-                                                        const void* dz, const void* v, void* out, long n,
-                                                        double alpha, double beta) {
+                                                        const void* dz, const void* v, void* out, unsigned n,
+                                                        double q4a, double beta) {
+  const unsigned i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= n) return;
   const Real* vx = reinterpret_cast<const Real*>(v);
-  const Real* vy = vx + n;
-  const Real* vz = vy + n;
-  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
-    const cplx<Real> p = ldc<Real>(phi, i), a = ldc<Real>(dx, i), b = ldc<Real>(dy, i), c = ldc<Real>(dz, i);
-    const double ux = vx[i], uy = vy[i], uz = vz[i];
-    const double gr = ux * a.x + uy * b.x + uz * c.x, gi = ux * a.y + uy * b.y + uz * c.y;   // v.grad phi
-    const double pr = p.x, pi = p.y;
-    const double f = beta - (ux * ux + uy * uy + uz * uz) / (4.0 * alpha) - beta * (pr * pr + pi * pi);
-    stc<Real>(out, i, gi + f * pr, -gr + f * pi);                                             // -i (gr + i gi) + f phi
-  }
+  const cplx<Real> p = ldc<Real>(phi, i), a = ldc<Real>(dx, i), b = ldc<Real>(dy, i), c = ldc<Real>(dz, i);
+  const double ux = vx[i], uy = vx[n + i], uz = vx[2u * n + i];
+  const double gr = ux * a.x + uy * b.x + uz * c.x, gi = ux * a.y + uy * b.y + uz * c.y;   // v.grad phi
+  const double pr = p.x, pi = p.y;
+  const double f = beta - (ux * ux + uy * uy + uz * uz) * q4a - beta * (pr * pr + pi * pi);
+  stc<Real>(out, i, gi + f * pr, -gr + f * pi);                                             // -i (gr + i gi) + f phi
 }
 
 // the implicit half of the Laplacian, diagonal in Fourier space, on unnormalised
 // transforms P = F(phi^n), Q = F(n): P <- ((1 - a k^2) P + dtau Q) / ((1 + a k^2) N^3),
-// a = dtau alpha / 2, |k|^2 with the Nyquist entry N^2/4
+// a = dtau alpha / 2, |k|^2 with the Nyquist entry N^2/4.  Grid: x = rows (y, z),
+// y = 256-point chunks of a row.
 template <class Real>
 __global__ __launch_bounds__(256) void k_argle_solve(void* P, const void* Q, int nx, int ny, int nz, double a,
                                                      double dtau, double inv_n) {
-  const long n = (long)nx * ny * nz;
-  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
-    const int ix = (int)(i % nx), iy = (int)((i / nx) % ny), iz = (int)(i / ((long)nx * ny));
-    const double kx = kfreq(ix, nx), ky = kfreq(iy, ny), kz = kfreq(iz, nz);
-    const double k2 = kx * kx + ky * ky + kz * kz;
-    const double num = 1.0 - a * k2, den = inv_n / (1.0 + a * k2);
-    const cplx<Real> p = ldc<Real>(P, i), q = ldc<Real>(Q, i);
-    stc<Real>(P, i, (num * (double)p.x + dtau * (double)q.x) * den, (num * (double)p.y + dtau * (double)q.y) * den);
-  }
+  const int ix = blockIdx.y * 256 + threadIdx.x;
+  if (ix >= nx) return;
+  const unsigned row = blockIdx.x;                     // uniform: iy, iz on the scalar unit
+  const int iy = (int)(row % (unsigned)ny), iz = (int)(row / (unsigned)ny);
+  const unsigned i = row * (unsigned)nx + (unsigned)ix;
+  const double kx = kfreq(ix, nx), ky = kfreq(iy, ny), kz = kfreq(iz, nz);
+  const double k2 = kx * kx + ky * ky + kz * kz;
+  const double num = 1.0 - a * k2, den = inv_n / (1.0 + a * k2);
+  const cplx<Real> p = ldc<Real>(P, i), q = ldc<Real>(Q, i);
+  stc<Real>(P, i, (num * (double)p.x + dtau * (double)q.x) * den, (num * (double)p.y + dtau * (double)q.y) * den);
 }
 
 // per-workgroup partial sums of alpha |grad phi - i v phi/(2 alpha)|^2 + (beta/2)(|phi|^2 - 1)^2
@@ -585,18 +586,20 @@ void launch_loss_lambda2(int prec, void* lam, const void* e0, const void* e1, co
 }
 void launch_argle_explicit(int prec, const void* phi, const void* dx, const void* dy, const void* dz, const void* v,
                            void* out, long n, double alpha, double beta, hipStream_t st) {
+  const unsigned blocks = (unsigned)((n + 255) / 256), un = (unsigned)n;
+  const double q4a = 1.0 / (4.0 * alpha);
   if (prec == P_C128)
-    hipLaunchKernelGGL(k_argle_explicit<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, phi, dx, dy, dz, v, out, n, alpha, beta);
+    hipLaunchKernelGGL(k_argle_explicit<double>, dim3(blocks), dim3(256), 0, st, phi, dx, dy, dz, v, out, un, q4a, beta);
   else
-    hipLaunchKernelGGL(k_argle_explicit<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, phi, dx, dy, dz, v, out, n, alpha, beta);
+    hipLaunchKernelGGL(k_argle_explicit<float>, dim3(blocks), dim3(256), 0, st, phi, dx, dy, dz, v, out, un, q4a, beta);
 }
 void launch_argle_solve(int prec, void* P, const void* Q, int nx, int ny, int nz, double a, double dtau, double inv_n,
                         hipStream_t st) {
-  const long n = (long)nx * ny * nz;
+  const dim3 grid((unsigned)(ny * nz), (unsigned)((nx + 255) / 256));
   if (prec == P_C128)
-    hipLaunchKernelGGL(k_argle_solve<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, P, Q, nx, ny, nz, a, dtau, inv_n);
+    hipLaunchKernelGGL(k_argle_solve<double>, grid, dim3(256), 0, st, P, Q, nx, ny, nz, a, dtau, inv_n);
   else
-    hipLaunchKernelGGL(k_argle_solve<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, P, Q, nx, ny, nz, a, dtau, inv_n);
+    hipLaunchKernelGGL(k_argle_solve<float>, grid, dim3(256), 0, st, P, Q, nx, ny, nz, a, dtau, inv_n);
 }
 void launch_argle_energy(int prec, const void* phi, const void* dx, const void* dy, const void* dz, const void* v,
                          long n, double alpha, double beta, double* partial, unsigned blocks, hipStream_t st) {
