@@ -38,6 +38,7 @@ __all__ = [
     "grids_k", "ksq", "linear_substep", "nonlinear_substep", "strang_step",
     "evolve", "mass", "energy", "gradient", "momentum_w", "quantum_q", "helmholtz",
     "shell_index", "nshell", "diagnostics", "structure_function_density",
+    "velocity", "structure_function_velocity", "mach_numbers",
     "table1_params", "gamma_d_quarter",
 ]
 
@@ -266,6 +267,42 @@ def structure_function_density(psi, p: int = 2):
             acc += float(np.mean((np.roll(rho, -m, axis=ax) - rho) ** p))
         out[m - 1] = acc / 3.0
     return out
+
+
+def velocity(psi, alpha, engine=None):
+    """Superfluid velocity v = 2 alpha Im(conj(psi) grad psi) / |psi|^2 (eq. scaling-rhov
+    divided by rho), 0 where |psi| = 0 exactly.  Returns [v_z, v_y, v_x]."""
+    d = gradient(psi, engine)
+    rho = np.abs(psi) ** 2
+    safe = np.where(rho > 0.0, rho, 1.0)
+    return [np.where(rho > 0.0, 2.0 * alpha * np.imag(np.conj(psi) * dj) / safe, 0.0) for dj in d]
+
+
+def structure_function_velocity(psi, alpha, p: int = 2, engine=None):
+    """Longitudinal velocity structure functions of eq. strfunc-def, one per axis,
+    by direct lag sums: S_j(m) = < (v_j(x + m dx e_j) - v_j(x))^p >, m = 1..N_j/2
+    (spatial mean over the periodic box).  Returns an array [3][N/2] in the order
+    (x, y, z) for a cubic grid, and <v_j^2> per axis (the large-lag limit of S_j is
+    2 <v_j^2> when v_j decorrelates, eq. strfunc-verif)."""
+    vz, vy, vx = velocity(psi, alpha, engine)
+    n = psi.shape[0]
+    out = np.zeros((3, n // 2))
+    comps = ((vx, 2), (vy, 1), (vz, 0))           # (component, array axis along it)
+    for j, (v, ax) in enumerate(comps):
+        for m in range(1, n // 2 + 1):
+            out[j, m - 1] = float(np.mean((np.roll(v, -m, axis=ax) - v) ** p))
+    mean_v2 = np.array([float(np.mean(v * v)) for v, _ in comps])
+    return out, mean_v2
+
+
+def mach_numbers(psi, alpha, beta, engine=None):
+    """Maximum and rms Mach numbers of eq. Mach-Number: M_max = max |sqrt(rho) v| / c,
+    M_rms = sqrt(2 E_kin) / c, with sqrt(rho) v = w and c = sqrt(2 alpha beta) (the sound
+    speed in the paper's scaling, from xi^2 c^2 = 2 alpha^2 and xi^2 = alpha / beta)."""
+    w, _ = momentum_w(psi, alpha, engine)
+    w2 = w[0] ** 2 + w[1] ** 2 + w[2] ** 2
+    c = math.sqrt(2.0 * alpha * beta)
+    return float(np.sqrt(w2.max())) / c, math.sqrt(float(np.mean(w2))) / c
 
 
 # ---------------------------------------------------------------- parameters

@@ -289,6 +289,82 @@ def test_structure_function_matches_autocorrelation():
     assert np.abs(s - ref / 3).max() < 1e-12
 
 
+def test_velocity_structure_function_closed_form():
+    """psi = exp(i a cos x) (|psi| = 1): v = -2 alpha a sin(x) e_x, so
+    S_x(m) = (2 alpha a)^2 (1 - cos(2 pi m / N)) and S_y = S_z = 0; <v_x^2> = 2 (alpha a)^2,
+    and the mean of S_x over all lags (S(N - m) = S(m)) is 2 <v_x^2>, the large-lag
+    value of eq. strfunc-verif for a decorrelating field.  The
+    spectral derivative of exp(i a cos x) is exact to round-off (its modes decay
+    like J_k(a))."""
+    n, alpha, a = 32, 0.3, 0.5
+    z, y, x = _grid3(n)
+    psi = np.exp(1j * a * np.cos(x)) * np.ones((n, n, n))
+    s, mv2 = gp.structure_function_velocity(psi, alpha)
+    r = 2 * np.pi * np.arange(1, n // 2 + 1) / n
+    assert np.abs(s[0] - (2 * alpha * a) ** 2 * (1 - np.cos(r))).max() < 1e-13
+    assert np.abs(s[1:]).max() < 1e-26
+    assert abs(mv2[0] - 2 * (alpha * a) ** 2) < 1e-14
+    assert abs((2 * s[0][:-1].sum() + s[0][-1]) / n - 2 * mv2[0]) < 1e-13
+    # y-dependence moves to the second row
+    psi_y = np.exp(1j * a * np.cos(y)) * np.ones((n, n, n))
+    s_y, _ = gp.structure_function_velocity(psi_y, alpha)
+    assert np.abs(s_y[1] - s[0]).max() < 1e-13 and np.abs(s_y[0]).max() < 1e-26
+
+
+def test_velocity_structure_function_matches_autocorrelation():
+    """On a random field (and a vortex-carrying one) the lag sums equal
+    2 (C(0) - C(m)) from the FFT autocorrelation of v_j along axis j."""
+    alpha = 0.25
+    for psi in (I.random_field(8, seed=4), I.tg_psi(16, 0.1, 1)):
+        n = psi.shape[0]
+        s, mv2 = gp.structure_function_velocity(psi, alpha)
+        vz, vy, vx = gp.velocity(psi, alpha)
+        for j, (v, ax) in enumerate(((vx, 2), (vy, 1), (vz, 0))):
+            f = np.fft.fft(v, axis=ax)
+            c = np.real(np.fft.ifft(np.abs(f) ** 2, axis=ax))
+            c = np.mean(np.moveaxis(c, ax, 0), axis=(1, 2)) / n
+            assert np.abs(s[j] - 2 * (c[0] - c[1:n // 2 + 1])).max() < 1e-11 * max(1.0, c[0])
+            assert abs(mv2[j] - c[0]) < 1e-12 * max(1.0, c[0])
+
+
+def test_velocity_is_momentum_over_amplitude():
+    """v = w / sqrt(rho) (eq. scaling-rhov), 0 where psi = 0; for a plane wave
+    A exp(i k.x), v = 2 alpha k."""
+    n, alpha = 16, 0.35
+    psi = plane_wave(n, 1, -2, 3, 1.7)
+    v = gp.velocity(psi, alpha)
+    for j, k in enumerate((1, -2, 3)):
+        assert np.abs(v[j] - 2 * alpha * k).max() < 1e-12
+    psi = I.random_field(8, seed=9)
+    psi[0, 0, 0] = 0
+    v = gp.velocity(psi, alpha)
+    w, _ = gp.momentum_w(psi, alpha)
+    amp = np.abs(psi)
+    for j in range(3):
+        assert v[j][0, 0, 0] == 0.0
+        m = amp > 0
+        assert np.abs(v[j][m] * amp[m] - w[j][m]).max() < 1e-12
+
+
+def test_mach_numbers():
+    """Plane wave A exp(i k.x): |w| = 2 alpha |k| A everywhere, so M_max = M_rms =
+    2 alpha |k| A / c with c = sqrt(2 alpha beta); on any field M_rms = sqrt(2 E_kin)/c
+    (eq. Mach-Number) and M_max >= M_rms.  The paper's Mach table is consistent with
+    c = 2 at alpha beta = 2: its M_rms of ABC_c equals sqrt(2 (E_kin^i + E_kin^c))/2 of
+    the printed ABC_cIT energies."""
+    n, alpha, beta, A = 16, 0.3, 2.0, 1.2
+    k = (1, -2, 3)
+    mmax, mrms = gp.mach_numbers(plane_wave(n, *k, A), alpha, beta)
+    want = 2 * alpha * math.sqrt(sum(x * x for x in k)) * A / math.sqrt(2 * alpha * beta)
+    assert abs(mmax - want) < 1e-12 and abs(mrms - want) < 1e-12
+    psi = I.random_field(12, seed=5)
+    mmax, mrms = gp.mach_numbers(psi, alpha, beta)
+    d = gp.diagnostics(psi, alpha, beta)
+    assert abs(mrms - math.sqrt(2 * d["e_kin"]) / math.sqrt(2 * alpha * beta)) < 1e-12 and mmax > mrms
+    e_kin_c = 0.9884992 + 0.0006486                 # ABC_cIT, E_kin^i + E_kin^c
+    assert abs(math.sqrt(2 * e_kin_c) / 2.0 - 0.703259) < 2e-6
+
+
 # ------------------------------------------------------------------ parameters
 def _golden_table1():
     rows = []
