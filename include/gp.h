@@ -156,6 +156,22 @@ GP_API gp_status gp_spectra(gp_plan_t* p, const void* psi, void* work, double* o
  * m = 1 .. Nx/2 (cubic grids only).  p_order must be 2.  Synchronizes. */
 GP_API gp_status gp_structure_fn(gp_plan_t* p, const void* psi, void* work, int32_t p_order, double* out);
 
+/* Longitudinal velocity structure functions (eq. strfunc-def), one per axis:
+ * S_j(m) = < (v_j(x + m dx e_j) - v_j(x))^2 >, spatial mean, lags m = 1 .. N/2, with
+ * v = 2 alpha Im(conj(psi) grad psi)/|psi|^2 from the spectral derivatives (v = 0 where
+ * psi = 0).  Computed from the power spectrum of v_j along axis j (Wiener-Khinchin).
+ * out: host, 3 * (N/2) doubles [axis (x, y, z)][m]; mean_v2: host, 3 doubles <v_j^2>
+ * (2 <v_j^2> is the large-lag value of eq. strfunc-verif), may be NULL.  Cubic grids
+ * only; p_order must be 2.  work: dev, gp_work_bytes.  Synchronizes. */
+GP_API gp_status gp_structure_fn_velocity(gp_plan_t* p, const void* psi, void* work, int32_t p_order, double* out,
+                                          double* mean_v2);
+
+/* Mach numbers (eq. Mach-Number): out[0] = M_max = max |sqrt(rho) v| / c,
+ * out[1] = M_rms = sqrt(2 E_kin) / c, with sqrt(rho) v = w of gp_energy and the sound
+ * speed c = sqrt(2 alpha beta) of the paper's scaling.  out: host, 2 doubles.
+ * work: dev, gp_work_bytes.  Synchronizes. */
+GP_API gp_status gp_mach(gp_plan_t* p, const void* psi, void* work, double* out);
+
 /* Loss J = 1/2 sum over shells smin..smax of |w^i_k|^2 (incompressible kinetic
  * energy spectrum summed over those shells) and its gradient lam (dev, out) with
  * dJ = Re sum conj(lam) dpsi.  J: host.  Synchronizes. */

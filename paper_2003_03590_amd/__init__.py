@@ -214,6 +214,24 @@ class Plan:
                                      out.ctypes.data_as(C.POINTER(C.c_double))))
         return out
 
+    def structure_fn_velocity(self, psi, p_order: int = 2):
+        """Longitudinal velocity structure functions per axis: (S [3][N/2] in the
+        order x, y, z, <v_j^2> [3])."""
+        half = self.n[0] // 2
+        out = np.zeros((3, half), dtype=np.float64)
+        mv2 = np.zeros(3, dtype=np.float64)
+        _check(lib().gp_structure_fn_velocity(self._h, self._field(psi), C.c_void_p(_ptr(self.work())), int(p_order),
+                                              out.ctypes.data_as(C.POINTER(C.c_double)),
+                                              mv2.ctypes.data_as(C.POINTER(C.c_double))))
+        return out, mv2
+
+    def mach(self, psi):
+        """(M_max, M_rms)."""
+        out = np.zeros(2, dtype=np.float64)
+        _check(lib().gp_mach(self._h, self._field(psi), C.c_void_p(_ptr(self.work())),
+                             out.ctypes.data_as(C.POINTER(C.c_double))))
+        return float(out[0]), float(out[1])
+
     def loss_ekin_i_shells(self, psi, smin: int, smax: int, lam=None):
         lam = self.empty() if lam is None else lam
         J = C.c_double()

@@ -18,6 +18,15 @@ void launch_spectral(int prec, const void* F0, const void* F1, const void* F2, c
 // out[0] = max over the field of |a - b|^2 (partial: blocks doubles)
 void launch_sup_diff2(int prec, const void* a, const void* b, long n, double* partial, unsigned blocks, double* out,
                       hipStream_t st);
+// in place: d_a <- v_a + 0i (superfluid velocity); partial[3][blocks] = sum v_a^2
+void launch_velocity_fields(int prec, const void* psi, void* d0, void* d1, void* d2, long n, double alpha,
+                            double* partial, unsigned blocks, hipStream_t st);
+// psum, pmax: `blocks` doubles each (sum and max of |w|^2 per block)
+void launch_mach_partials(int prec, const void* psi, const void* d0, const void* d1, const void* d2, long n,
+                          double alpha, double* psum, double* pmax, unsigned blocks, hipStream_t st);
+void launch_segmax(const double* in, long len, double* out, hipStream_t st);
+// out[3][nj/2] per-axis structure functions from pk[3][nj]
+void launch_structure_axes(const double* pk, int nj, double ntot, double* out, hipStream_t st);
 void launch_segsum(const double* in, long len, int nseg, double* out, hipStream_t st);
 void launch_finalize_diag(const double* red, double w0, double w1, double w2, int nshell, double alpha, double beta,
                           double ntot, double* out, hipStream_t st);

@@ -510,6 +510,81 @@ __global__ __launch_bounds__(256) void k_structure_final(const double* __restric
   }
 }
 
+// ----------------------------------------------------------------- velocity statistics
+// Superfluid velocity v = 2 alpha Im(conj(psi) grad psi)/|psi|^2 (0 where psi = 0).
+// In: d0, d1, d2 = spectral derivatives of psi along x, y, z.  Out (in place):
+// d_a = v_a + 0i for the transform along axis a; partial[a][block] = sum v_a^2.
+template <class Real>
+__global__ __launch_bounds__(256) void k_velocity_fields(const void* psi, void* d0, void* d1, void* d2, unsigned n,
+                                                         double alpha, double* __restrict__ partial) {
+  __shared__ double sh[4];
+  Neu acc[3];
+  void* d[3] = {d0, d1, d2};
+  for (unsigned i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) {
+    const cplx<Real> p = ldc<Real>(psi, i);
+    const double pr = p.x, pi = p.y, rho = pr * pr + pi * pi;
+    const double f = rho > 0.0 ? 2.0 * alpha / rho : 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const cplx<Real> g = ldc<Real>(d[a], i);
+      const double v = f * (pr * (double)g.y - pi * (double)g.x);
+      stc<Real>(d[a], i, v, 0.0);
+      acc[a].add(v * v);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double t = block_sum256(acc[a].val(), sh);
+    if (threadIdx.x == 0) partial[(long)a * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+// Mach-number partials: sum |w|^2 and max |w|^2 per block, w = sqrt(rho) v.
+template <class Real>
+__global__ __launch_bounds__(256) void k_mach_partials(const void* psi, const void* d0, const void* d1, const void* d2,
+                                                       unsigned n, double alpha, double* __restrict__ psum,
+                                                       double* __restrict__ pmax) {
+  __shared__ double sh[4];
+  Neu acc;
+  double mx = 0.0;
+  for (unsigned i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) {
+    const cplx<Real> p = ldc<Real>(psi, i);
+    const cplx<Real> g[3] = {ldc<Real>(d0, i), ldc<Real>(d1, i), ldc<Real>(d2, i)};
+    const double pr = p.x, pi = p.y, rho = pr * pr + pi * pi;
+    double w2 = 0.0;
+    if (rho > 0.0) {
+      double im2 = 0.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double im = pr * (double)g[a].y - pi * (double)g[a].x;
+        im2 += im * im;
+      }
+      w2 = 4.0 * alpha * alpha * im2 / rho;
+    }
+    acc.add(w2);
+    mx = fmax(mx, w2);
+  }
+  const double s = block_sum256(acc.val(), sh);
+  const double m = block_max256(mx, sh);
+  if (threadIdx.x == 0) { psum[blockIdx.x] = s; pmax[blockIdx.x] = m; }
+}
+
+// Per-axis structure functions S_a(m) = 2/(Ntot N) sum_k P_a(k) (1 - cos(2 pi k m / N)),
+// m = 1..N/2, from the reduced power sums pk[axis][k] of v_a transformed along axis a.
+__global__ __launch_bounds__(256) void k_structure_axes(const double* __restrict__ pk, int nj, double ntot,
+                                                        double* __restrict__ out) {
+  const int half = nj / 2;
+  for (int q = threadIdx.x; q < 3 * half; q += 256) {
+    const int ax = q / half, m = q % half + 1;
+    Neu a;
+    for (int k = 0; k < nj; ++k) {
+      const long km = ((long)k * m) % nj;
+      a.add(pk[ax * nj + k] * (1.0 - cospi(2.0 * (double)km / (double)nj)));
+    }
+    out[q] = a.val() * 2.0 / (ntot * (double)nj);
+  }
+}
+
 // ----------------------------------------------------------------- launch wrappers
 static unsigned grid_for(long n, int threads, unsigned cap = 4096) {
   long g = (n + threads - 1) / threads;
@@ -617,6 +692,26 @@ void launch_axis_power(int prec, const void* F, long n, long div, int nj, unsign
   const size_t sh = sizeof(double) * (size_t)nj;
   if (prec == P_C128) hipLaunchKernelGGL(k_axis_power_c128, dim3(blocks), dim3(64), sh, st, F, n, div, nj, chunk, part);
   else hipLaunchKernelGGL(k_axis_power_c64, dim3(blocks), dim3(64), sh, st, F, n, div, nj, chunk, part);
+}
+void launch_velocity_fields(int prec, const void* psi, void* d0, void* d1, void* d2, long n, double alpha,
+                            double* partial, unsigned blocks, hipStream_t st) {
+  if (prec == P_C128)
+    hipLaunchKernelGGL(k_velocity_fields<double>, dim3(blocks), dim3(256), 0, st, psi, d0, d1, d2, (unsigned)n, alpha, partial);
+  else
+    hipLaunchKernelGGL(k_velocity_fields<float>, dim3(blocks), dim3(256), 0, st, psi, d0, d1, d2, (unsigned)n, alpha, partial);
+}
+void launch_mach_partials(int prec, const void* psi, const void* d0, const void* d1, const void* d2, long n,
+                          double alpha, double* psum, double* pmax, unsigned blocks, hipStream_t st) {
+  if (prec == P_C128)
+    hipLaunchKernelGGL(k_mach_partials<double>, dim3(blocks), dim3(256), 0, st, psi, d0, d1, d2, (unsigned)n, alpha, psum, pmax);
+  else
+    hipLaunchKernelGGL(k_mach_partials<float>, dim3(blocks), dim3(256), 0, st, psi, d0, d1, d2, (unsigned)n, alpha, psum, pmax);
+}
+void launch_segmax(const double* in, long len, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_segmax, dim3(1), dim3(256), 0, st, in, len, out);
+}
+void launch_structure_axes(const double* pk, int nj, double ntot, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_structure_axes, dim3(1), dim3(256), 0, st, pk, nj, ntot, out);
 }
 void launch_structure_final(const double* pk, int nj, double ntot, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_structure_final, dim3(1), dim3(256), 0, st, pk, nj, ntot, out);

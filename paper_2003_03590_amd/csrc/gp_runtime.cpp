@@ -874,6 +874,66 @@ gp_status gp_structure_fn(gp_plan_t* p, const void* psi, void* work, int32_t p_o
   return GP_OK;
 }
 
+gp_status gp_structure_fn_velocity(gp_plan_t* p, const void* psi, void* work, int32_t p_order, double* out,
+                                   double* mean_v2) {
+  gp_status st = usable(p);
+  if (st != GP_OK) return st;
+  if (p->is_batch) return fail(GP_ERR_STATE, "batch plan: diagnostics run on single plans");
+  if (!psi || !work || !out) return fail(GP_ERR_ARG, "null argument");
+  if (p_order != 2) return fail(GP_ERR_UNSUPPORTED, "structure function order %d (only 2)", p_order);
+  const int n = p->d.n[0];
+  if (p->d.n[1] != n || p->d.n[2] != n) return fail(GP_ERR_UNSUPPORTED, "structure function needs a cubic grid");
+  if (n < 2) return fail(GP_ERR_UNSUPPORTED, "structure function needs n >= 2");
+  if ((st = derivatives(p, psi, work, false)) != GP_OK) return st;
+  void* f[3] = {field(p, work, 0), field(p, work, 1), field(p, work, 2)};
+  launch_velocity_fields(p->prec, psi, f[0], f[1], f[2], p->ntot, p->d.alpha, p->field_part, p->field_blocks, p->stream);
+  if ((st = check_launch(p)) != GP_OK) return st;
+  const long div[3] = {1, n, (long)n * n};
+  for (int a = 0; a < 3; ++a) {
+    // F_a(v_a), natural order along axis a
+    if ((st = pass(p, a, V_FWD, f[a], f[a], nullptr, 0.0, nullptr, 1.0)) != GP_OK) return st;
+    launch_axis_power(p->prec, f[a], p->ntot, div[a], n, p->pow_blocks, p->pow_chunk,
+                      p->power_part + (size_t)a * p->pow_blocks * n, p->stream);
+    if ((st = check_launch(p)) != GP_OK) return st;
+  }
+  const int half = n / 2;
+  launch_segsum(p->power_part, p->pow_blocks, 3 * n, p->d_pk, p->stream);
+  launch_structure_axes(p->d_pk, n, (double)p->ntot, p->d_result, p->stream);
+  launch_segsum(p->field_part, p->field_blocks, 3, p->d_result + 3 * half, p->stream);
+  if ((st = check_launch(p)) != GP_OK) return st;
+  HIPCHK(p, hipMemcpyAsync(p->h_result, p->d_result, (3 * half + 3) * sizeof(double), hipMemcpyDeviceToHost,
+                           p->stream));
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  memcpy(out, p->h_result, 3 * half * sizeof(double));
+  if (mean_v2)
+    for (int a = 0; a < 3; ++a) mean_v2[a] = p->h_result[3 * half + a] / (double)p->ntot;
+  for (int q = 0; q < 3 * half; ++q)
+    if (!std::isfinite(out[q])) return fail(GP_ERR_NONFINITE, "velocity structure function is not finite");
+  return GP_OK;
+}
+
+gp_status gp_mach(gp_plan_t* p, const void* psi, void* work, double* out) {
+  gp_status st = usable(p);
+  if (st != GP_OK) return st;
+  if (p->is_batch) return fail(GP_ERR_STATE, "batch plan: diagnostics run on single plans");
+  if (!psi || !work || !out) return fail(GP_ERR_ARG, "null argument");
+  if (!(p->d.alpha * p->d.beta > 0.0)) return fail(GP_ERR_ARG, "Mach numbers need alpha beta > 0");
+  if ((st = derivatives(p, psi, work, false)) != GP_OK) return st;
+  launch_mach_partials(p->prec, psi, field(p, work, 0), field(p, work, 1), field(p, work, 2), p->ntot, p->d.alpha,
+                       p->loss_part, p->field_part, p->field_blocks, p->stream);
+  if ((st = check_launch(p)) != GP_OK) return st;
+  launch_segsum(p->loss_part, p->field_blocks, 1, p->d_result, p->stream);
+  launch_segmax(p->field_part, p->field_blocks, p->d_result + 1, p->stream);
+  if ((st = check_launch(p)) != GP_OK) return st;
+  HIPCHK(p, hipMemcpyAsync(p->h_result, p->d_result, 2 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  const double c = std::sqrt(2.0 * p->d.alpha * p->d.beta);
+  out[0] = std::sqrt(p->h_result[1]) / c;
+  out[1] = std::sqrt(p->h_result[0] / (double)p->ntot) / c;
+  if (!std::isfinite(out[0]) || !std::isfinite(out[1])) return fail(GP_ERR_NONFINITE, "Mach number is not finite");
+  return GP_OK;
+}
+
 // nsteps steps of the semi-implicit backward Euler scheme; work slots 0..2.  The
 // explicit part n overwrites d/dz in place (its only reader), which streams faster
 // than writing a separate field.
