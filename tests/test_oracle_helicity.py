@@ -1,0 +1,82 @@
+"""Pins of the helicity oracle (section "Helicity": eq. helicity, eq. Hreg and the
+regularized velocity) against exact cases and the symmetries helicity obeys."""
+import numpy as np
+
+import gp_inputs as I
+from oracle import helicity as Hh
+from oracle import gp
+
+
+def _grid3(n):
+    x = 2 * np.pi * np.arange(n) / n
+    return x[:, None, None], x[None, :, None], x[None, None, :]   # z, y, x
+
+
+def test_v_parallel_on_straight_vortex_lines_is_the_axial_flow():
+    """psi = (sin x + i sin y) exp(i k z) has straight vortex lines along z through
+    (0, 0), (pi, 0), (0, pi), (pi, pi) with windings +1, -1, -1, +1 and axial velocity
+    2 alpha k.  At the cores W/|W| = +-z (the sign of the winding) and v_par W/|W| is
+    the axial flow 2 alpha k z for both windings (band-limited: derivatives exact)."""
+    n, k, alpha = 16, 2, 0.3
+    z, y, x = _grid3(n)
+    psi = (np.sin(x) + 1j * np.sin(y)) * np.exp(1j * k * z) * np.ones((n, n, n))
+    vpar, unit = Hh.v_parallel(psi, alpha)
+    h = n // 2
+    for (iy, ix), wind in (((0, 0), 1), ((0, h), -1), ((h, 0), -1), ((h, h), 1)):
+        assert np.abs(unit[0][:, iy, ix] - wind).max() < 1e-12
+        assert np.abs(unit[1][:, iy, ix]).max() < 1e-12 and np.abs(unit[2][:, iy, ix]).max() < 1e-12
+        assert np.abs(vpar[:, iy, ix] * unit[0][:, iy, ix] - 2 * alpha * k).max() < 1e-12
+
+
+def test_pseudo_vorticity_is_the_curl_of_the_momentum_density():
+    """W = 4 alpha grad(Re psi) x grad(Im psi) equals curl(rho v) with
+    rho v = 2 alpha Im(psi* grad psi) (band-limited field, so exact)."""
+    n, alpha = 16, 0.4
+    z, y, x = _grid3(n)
+    # wavenumbers <= 2 per axis: the products below reach 4 < N/2, no aliasing
+    psi = np.cos(x) + 0.5j * np.sin(y + z) + 0.3 * np.sin(2 * y) + 0.2j * np.cos(x - 2 * z) + 0.4
+    d = gp.gradient(psi)
+    j = [2 * alpha * np.imag(np.conj(psi) * dj) for dj in d]
+    W = Hh.pseudo_vorticity(psi, alpha)
+    c = Hh.curl(j)
+    assert max(np.abs(W[i] - c[i]).max() for i in range(3)) < 1e-12
+    assert max(np.abs(W[i]).max() for i in range(3)) > 0.1
+
+
+def test_curl_of_abc_flows():
+    """curl v^(k) = k v^(k) for the ABC flow of wavenumber k (eq. ABC): the oracle's
+    curl, component by component."""
+    for k in (1, 2):
+        v = I.abc_velocity(16, ks=(k,))
+        w = Hh.curl(v)
+        assert max(np.abs(w[i] - k * v[i]).max() for i in range(3)) < 1e-12
+
+
+def test_gradient_flow_has_no_helicity():
+    """psi = A exp(i theta) with smooth A and smooth theta: v = 2 alpha grad theta, so
+    omega = 0 and H = H_reg = 0 (up to the spectral truncation of exp(i theta)).  The
+    phase carries a uniform drift so that grad psi vanishes nowhere: the regularized
+    velocity divides by |grad psi|^2 and is singular at stagnation points of psi."""
+    n, alpha = 32, 0.3
+    z, y, x = _grid3(n)
+    theta = x + 0.3 * np.sin(x + 2 * y) + 0.2 * np.cos(z - y)
+    amp = 1.0 + 0.1 * np.cos(x) * np.sin(z)
+    r = Hh.helicity(amp * np.exp(1j * theta), alpha)
+    assert abs(r["H"]) < 1e-12 and abs(r["H_reg"]) < 1e-12
+
+
+def test_helicity_is_a_pseudoscalar():
+    """A mirror image x -> -x flips H and H_reg; complex conjugation (v -> -v,
+    omega -> -omega) leaves them unchanged; the spectra sum to the helicities."""
+    alpha = 0.25
+    psi = I.random_field(12, seed=7)
+    r = Hh.helicity(psi, alpha)
+    assert abs(r["H"]) > 1e-3 and abs(r["H_reg"]) > 1e-6
+    idx = (-np.arange(12)) % 12
+    rm = Hh.helicity(psi[:, :, idx], alpha)
+    rc = Hh.helicity(np.conj(psi), alpha)
+    for key in ("H", "H_reg"):
+        assert abs(rm[key] + r[key]) < 1e-10 * abs(r["H"]) + 1e-12
+        assert abs(rc[key] - r[key]) < 1e-10 * abs(r["H"]) + 1e-12
+    assert abs(r["spec"][0].sum() - r["H"]) < 1e-10 * abs(r["H"])
+    assert abs(r["spec"][1].sum() - r["H_reg"]) < 1e-9 * max(abs(r["H_reg"]), 1e-6)
