@@ -172,6 +172,24 @@ GP_API gp_status gp_structure_fn_velocity(gp_plan_t* p, const void* psi, void* w
  * work: dev, gp_work_bytes.  Synchronizes. */
 GP_API gp_status gp_mach(gp_plan_t* p, const void* psi, void* work, double* out);
 
+/* Bytes of the workspace gp_helicity needs (8 states; 0 for batch plans). */
+GP_API size_t gp_helicity_work_bytes(const gp_plan_t* p);
+
+/* Helicity and regularized helicity per unit volume (section on helicity):
+ *   out[0] = H     = < v . omega >                          (eq. helicity)
+ *   out[1] = H_reg = < v_reg . omega >                      (eq. Hreg)
+ * with v = 2 alpha Im(conj(psi) grad psi)/|psi|^2, omega = curl v (spectral),
+ * v_reg = v_par W/|W|, W = 4 alpha grad(Re psi) x grad(Im psi),
+ * v_par = 2 alpha W . J / (|W| |grad psi|^2), J_i = Im(sum_j (d_i d_j psi)(d_j psi)*)
+ * (hbar/m -> 2 alpha in the paper's scaling; v = 0 where psi = 0; v_reg = 0 where W = 0
+ * or |grad psi|^2 <= 1e-12 <|grad psi|^2>, the critical points of psi where v_par's
+ * denominator vanishes).  All derivatives spectral with the Nyquist entry 0; second
+ * derivatives are two first derivatives.  spec (host, may be NULL): [2][nshell] shell
+ * spectra Re(conj(v_k) . omega_k) and Re(conj(vreg_k) . omega_k), each summing to its
+ * helicity; nshell must equal gp_nshell.  work: dev, gp_helicity_work_bytes.
+ * Synchronizes. */
+GP_API gp_status gp_helicity(gp_plan_t* p, const void* psi, void* work, double* out, double* spec, int32_t nshell);
+
 /* Loss J = 1/2 sum over shells smin..smax of |w^i_k|^2 (incompressible kinetic
  * energy spectrum summed over those shells) and its gradient lam (dev, out) with
  * dJ = Re sum conj(lam) dpsi.  J: host.  Synchronizes. */

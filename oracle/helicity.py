@@ -13,7 +13,11 @@ with omega = curl v, and the regularized helicity H_reg = <v_reg . omega>
               J_i = Im( sum_j (d_i d_j psi) (d_j psi)* )
     v_reg   = v_par W / |W|      (0 where |W| = 0 or grad psi = 0).
 
-Readings: all derivatives are spectral with the first-derivative wavenumbers
+Readings: v_par divides by |grad psi|^2, which vanishes at the critical points
+of psi (not at vortex cores, where |grad psi|^2 ~ 1/(2 xi^2)); there v_reg is
+set to 0 where |grad psi|^2 <= 1e-12 <|grad psi|^2> (a symmetric field such as
+the Taylor-Green state has such points exactly on the grid, and the quantum
+vorticity vanishes there).  All derivatives are spectral with the first-derivative wavenumbers
 (Nyquist entry 0), second derivatives are two first derivatives (-k_i k_j);
 v = 2 alpha Im(psi* grad psi)/|psi|^2 (0 where psi = 0); omega = curl v taken
 spectrally from that v.  Spectra: integer shells round(|k|), H(k) = sum over the
@@ -27,7 +31,9 @@ import numpy as np
 from .fft import fft3, ifft3
 from .gp import first_derivative_k, gradient, grids_k, nshell, shell_index, velocity
 
-__all__ = ["derivative", "curl", "pseudo_vorticity", "v_parallel", "helicity"]
+__all__ = ["derivative", "curl", "pseudo_vorticity", "v_parallel", "helicity", "G2_FLOOR"]
+
+G2_FLOOR = 1e-12     # v_reg = 0 where |grad psi|^2 <= G2_FLOOR <|grad psi|^2>
 
 
 def derivative(f, axis: int, engine=None):
@@ -63,14 +69,15 @@ def pseudo_vorticity(psi, alpha, engine=None):
 
 
 def v_parallel(psi, alpha, engine=None):
-    """v_par and the unit vector W/|W| ([z, y, x]); both 0 where |W| or grad psi vanish."""
+    """v_par and the unit vector W/|W| ([z, y, x]); both 0 where |W| = 0 or
+    |grad psi|^2 <= G2_FLOOR <|grad psi|^2>."""
     d = gradient(psi, engine)                      # [d_z, d_y, d_x] psi
     hess = [[derivative(d[j], i, engine) for j in range(3)] for i in range(3)]   # hess[i][j] = d_i d_j psi
     J = [np.imag(sum(hess[i][j] * np.conj(d[j]) for j in range(3))) for i in range(3)]
     W = pseudo_vorticity(psi, alpha, engine)
     wn = np.sqrt(W[0] ** 2 + W[1] ** 2 + W[2] ** 2)
     g2 = sum(np.abs(dj) ** 2 for dj in d)
-    ok = (wn > 0.0) & (g2 > 0.0)
+    ok = (wn > 0.0) & (g2 > G2_FLOOR * float(np.mean(g2)))
     wn_s = np.where(ok, wn, 1.0)
     g2_s = np.where(ok, g2, 1.0)
     vpar = np.where(ok, 2.0 * alpha * (W[0] * J[0] + W[1] * J[1] + W[2] * J[2]) / (wn_s * g2_s), 0.0)

@@ -72,6 +72,7 @@ class Plan:
         self._h = h
         self.nshell = int(lib().gp_nshell(h))
         self._work = None
+        self._hwork = None
 
     # ---------------------------------------------------------------- plumbing
     def close(self):
@@ -224,6 +225,20 @@ class Plan:
                                               out.ctypes.data_as(C.POINTER(C.c_double)),
                                               mv2.ctypes.data_as(C.POINTER(C.c_double))))
         return out, mv2
+
+    def helicity(self, psi, spectra: bool = True):
+        """(H, H_reg) per unit volume and, with `spectra`, their shell spectra [2][nshell].
+        Uses a workspace of gp_helicity_work_bytes (8 states), allocated on first use."""
+        if self._hwork is None:
+            nb = int(lib().gp_helicity_work_bytes(self._h))
+            self._hwork = _torch().empty(nb, dtype=_torch().uint8, device=self.device)
+        out = np.zeros(2, dtype=np.float64)
+        spec = np.zeros((2, self.nshell), dtype=np.float64) if spectra else None
+        _check(lib().gp_helicity(self._h, self._field(psi), C.c_void_p(_ptr(self._hwork)),
+                                 out.ctypes.data_as(C.POINTER(C.c_double)),
+                                 spec.ctypes.data_as(C.POINTER(C.c_double)) if spectra else None,
+                                 self.nshell))
+        return (float(out[0]), float(out[1]), spec) if spectra else (float(out[0]), float(out[1]))
 
     def mach(self, psi):
         """(M_max, M_rms)."""

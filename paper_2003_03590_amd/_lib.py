@@ -67,6 +67,8 @@ SIGNATURES = {
     "gp_argle_energy": (ST, [P, P, P, P, C.POINTER(C.c_double)]),
     "gp_structure_fn_velocity": (ST, [P, P, P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "gp_mach": (ST, [P, P, P, C.POINTER(C.c_double)]),
+    "gp_helicity_work_bytes": (C.c_size_t, [P]),
+    "gp_helicity": (ST, [P, P, P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32]),
     "gp_argle_run": (ST, [P, P, P, C.c_double, C.c_int64, C.c_int64, C.c_double, P, C.POINTER(gp_argle_report)]),
     "gp_step_n_batch": (ST, [P, PP, C.c_int64]),
     "gp_energies_batch": (ST, [P, PP, P, C.POINTER(C.c_double)]),

@@ -25,6 +25,24 @@ void launch_velocity_fields(int prec, const void* psi, void* d0, void* d1, void*
 void launch_mach_partials(int prec, const void* psi, const void* d0, const void* d1, const void* d2, long n,
                           double alpha, double* psum, double* pmax, unsigned blocks, hipStream_t st);
 void launch_segmax(const double* in, long len, double* out, hipStream_t st);
+// helicity stages (see the kernels for the packing of real fields into states)
+// partial: blocks doubles (sum |grad psi|^2)
+void launch_hel_pack(int prec, const void* psi, const void* d0, const void* d1, const void* d2, void* s3, void* s4,
+                     void* s5, long n, double alpha, double* partial, unsigned blocks, hipStream_t st);
+void launch_hel_omega(int prec, const void* t3, const void* t4, const void* t5, void* s6, void* s7, long n,
+                      hipStream_t st);
+void launch_hel_acc(int prec, const void* H, const void* F1, int t1, const void* F2, int t2, int first, void* J0,
+                    void* J1, long n, hipStream_t st);
+// g2_sum: device, one double (sum |grad psi|^2); partial: 2 * blocks doubles
+void launch_hel_vreg(int prec, const void* psi, const void* d0, const void* d1, const void* d2, const void* j01,
+                     const void* j2, const void* w01, const void* w2, void* s3, void* s4, long n, double alpha,
+                     const double* g2_sum, double* partial, unsigned blocks, hipStream_t st);
+void launch_hel_vpack(int prec, const void* psi, void* d0, void* d1, const void* d2, long n, double alpha,
+                      hipStream_t st);
+// bins: blocks * 2 * nshell doubles
+void launch_hel_spectral(int prec, const void* V01, const void* V2, const void* R01, const void* R2, const void* O01,
+                         const void* O2, int nx, int ny, int nz, int nshell, unsigned blocks, long chunk,
+                         double* bins, hipStream_t st);
 // out[3][nj/2] per-axis structure functions from pk[3][nj]
 void launch_structure_axes(const double* pk, int nj, double ntot, double* out, hipStream_t st);
 void launch_segsum(const double* in, long len, int nseg, double* out, hipStream_t st);

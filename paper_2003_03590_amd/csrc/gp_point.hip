@@ -585,6 +585,187 @@ __global__ __launch_bounds__(256) void k_structure_axes(const double* __restrict
   }
 }
 
+// ----------------------------------------------------------------- helicity
+// Section on helicity: H = <v . omega> (eq. helicity), H_reg = <v_reg . omega>
+// (eq. Hreg), with hbar/m -> 2 alpha.  Real fields are carried two per complex
+// state; every kernel is pointwise (one point per thread, 32-bit indices).
+
+__device__ __forceinline__ void vel_at(double pr, double pi, const double* gr, const double* gi, double alpha,
+                                       double* v) {
+  const double rho = pr * pr + pi * pi;
+  const double f = rho > 0.0 ? 2.0 * alpha / rho : 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) v[a] = f * (pr * gi[a] - pi * gr[a]);
+}
+
+// S3 = v_z + i v_x, S4 = v_y + i v_x, S5 = v_z + i v_y (for d/dy, d/dz, d/dx of omega);
+// partial[block] = sum |grad psi|^2
+template <class Real>
+__global__ __launch_bounds__(256) void k_hel_pack(const void* psi, const void* d0, const void* d1, const void* d2,
+                                                  void* s3, void* s4, void* s5, unsigned n, double alpha,
+                                                  double* __restrict__ partial) {
+  __shared__ double sh[4];
+  Neu acc;
+  for (unsigned i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) {
+    const cplx<Real> p = ldc<Real>(psi, i);
+    const cplx<Real> g[3] = {ldc<Real>(d0, i), ldc<Real>(d1, i), ldc<Real>(d2, i)};
+    const double gr[3] = {g[0].x, g[1].x, g[2].x}, gi[3] = {g[0].y, g[1].y, g[2].y};
+    double v[3];
+    vel_at(p.x, p.y, gr, gi, alpha, v);
+    stc<Real>(s3, i, v[2], v[0]);
+    stc<Real>(s4, i, v[1], v[0]);
+    stc<Real>(s5, i, v[2], v[1]);
+    acc.add(gr[0] * gr[0] + gi[0] * gi[0] + gr[1] * gr[1] + gi[1] * gi[1] + gr[2] * gr[2] + gi[2] * gi[2]);
+  }
+  const double t = block_sum256(acc.val(), sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// from T3 = d/dy (v_z + i v_x), T4 = d/dz (v_y + i v_x), T5 = d/dx (v_z + i v_y):
+// S6 = omega_x + i omega_y, S7 = omega_z
+template <class Real>
+__global__ __launch_bounds__(256) void k_hel_omega(const void* t3, const void* t4, const void* t5, void* s6, void* s7,
+                                                   unsigned n) {
+  const unsigned i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= n) return;
+  const cplx<Real> a = ldc<Real>(t3, i), b = ldc<Real>(t4, i), c = ldc<Real>(t5, i);
+  const double ox = (double)a.x - (double)b.x;      // d_y v_z - d_z v_y
+  const double oy = (double)b.y - (double)c.x;      // d_z v_x - d_x v_z
+  const double oz = (double)c.y - (double)a.y;      // d_x v_y - d_y v_x
+  stc<Real>(s6, i, ox, oy);
+  stc<Real>(s7, i, oz, 0.0);
+}
+
+// J_i = Im(sum_j (d_i d_j psi)(d_j psi)*), accumulated from one Hessian entry H_ij:
+// J[t1] += Im(conj(F1) H), and when t2 >= 0, J[t2] += Im(conj(F2) H).  J is packed as
+// J0 = J_x + i J_y, J1 = J_z; `first` starts the sums from zero.
+template <class Real>
+__global__ __launch_bounds__(256) void k_hel_acc(const void* H, const void* F1, int t1, const void* F2, int t2,
+                                                 int first, void* J0, void* J1, unsigned n) {
+  const unsigned i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= n) return;
+  double j[3] = {0.0, 0.0, 0.0};
+  if (!first) {
+    const cplx<Real> a = ldc<Real>(J0, i), b = ldc<Real>(J1, i);
+    j[0] = a.x; j[1] = a.y; j[2] = b.x;
+  }
+  const cplx<Real> h = ldc<Real>(H, i), f = ldc<Real>(F1, i);
+  j[t1] += (double)f.x * (double)h.y - (double)f.y * (double)h.x;
+  if (t2 >= 0) {
+    const cplx<Real> g = ldc<Real>(F2, i);
+    j[t2] += (double)g.x * (double)h.y - (double)g.y * (double)h.x;
+  }
+  stc<Real>(J0, i, j[0], j[1]);
+  stc<Real>(J1, i, j[2], 0.0);
+}
+
+// v_reg = v_par W/|W|, W = 4 alpha grad(Re psi) x grad(Im psi),
+// v_par = 2 alpha W.J/(|W| |grad psi|^2); v_reg = 0 where |W| = 0 or where
+// |grad psi|^2 <= g2_floor = 1e-12 <|grad psi|^2> (critical points of psi, where the
+// denominator vanishes; g2_sum[0] / n is the mean).
+// Out: S3 = vreg_x + i vreg_y, S4 = vreg_z (S4 held J_x + i J_y: read first);
+// partial[0][block] = sum v.omega, partial[1][block] = sum v_reg.omega.
+template <class Real>
+__global__ __launch_bounds__(256) void k_hel_vreg(const void* psi, const void* d0, const void* d1, const void* d2,
+                                                  const void* j01, const void* j2, const void* w01, const void* w2,
+                                                  void* s3, void* s4, unsigned n, double alpha,
+                                                  const double* __restrict__ g2_sum, double* __restrict__ partial) {
+  __shared__ double sh[4];
+  Neu hv, hr;
+  const double g2_floor = 1e-12 * g2_sum[0] / (double)n;
+  for (unsigned i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) {
+    const cplx<Real> p = ldc<Real>(psi, i);
+    const cplx<Real> g[3] = {ldc<Real>(d0, i), ldc<Real>(d1, i), ldc<Real>(d2, i)};
+    const double gr[3] = {g[0].x, g[1].x, g[2].x}, gi[3] = {g[0].y, g[1].y, g[2].y};
+    double v[3];
+    vel_at(p.x, p.y, gr, gi, alpha, v);
+    const cplx<Real> ja = ldc<Real>(j01, i), jb = ldc<Real>(j2, i);
+    const cplx<Real> oa = ldc<Real>(w01, i), ob = ldc<Real>(w2, i);
+    const double J[3] = {ja.x, ja.y, jb.x}, om[3] = {oa.x, oa.y, ob.x};
+    const double W[3] = {4.0 * alpha * (gr[1] * gi[2] - gr[2] * gi[1]), 4.0 * alpha * (gr[2] * gi[0] - gr[0] * gi[2]),
+                         4.0 * alpha * (gr[0] * gi[1] - gr[1] * gi[0])};
+    const double wn = sqrt(W[0] * W[0] + W[1] * W[1] + W[2] * W[2]);
+    double g2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) g2 += gr[a] * gr[a] + gi[a] * gi[a];
+    double vr[3] = {0.0, 0.0, 0.0};
+    if (wn > 0.0 && g2 > g2_floor) {
+      const double vpar = 2.0 * alpha * (W[0] * J[0] + W[1] * J[1] + W[2] * J[2]) / (wn * g2);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) vr[a] = vpar * (W[a] / wn);
+    }
+    stc<Real>(s3, i, vr[0], vr[1]);
+    stc<Real>(s4, i, vr[2], 0.0);
+    hv.add(v[0] * om[0] + v[1] * om[1] + v[2] * om[2]);
+    hr.add(vr[0] * om[0] + vr[1] * om[1] + vr[2] * om[2]);
+  }
+  const double a = block_sum256(hv.val(), sh);
+  const double b = block_sum256(hr.val(), sh);
+  if (threadIdx.x == 0) { partial[blockIdx.x] = a; partial[gridDim.x + blockIdx.x] = b; }
+}
+
+// in place: S0 = v_x + i v_y, S1 = v_z (from psi and its derivatives S0, S1, S2)
+template <class Real>
+__global__ __launch_bounds__(256) void k_hel_vpack(const void* psi, void* d0, void* d1, const void* d2, unsigned n,
+                                                   double alpha) {
+  const unsigned i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= n) return;
+  const cplx<Real> p = ldc<Real>(psi, i);
+  const cplx<Real> g[3] = {ldc<Real>(d0, i), ldc<Real>(d1, i), ldc<Real>(d2, i)};
+  const double gr[3] = {g[0].x, g[1].x, g[2].x}, gi[3] = {g[0].y, g[1].y, g[2].y};
+  double v[3];
+  vel_at(p.x, p.y, gr, gi, alpha, v);
+  stc<Real>(d0, i, v[0], v[1]);
+  stc<Real>(d1, i, v[2], 0.0);
+}
+
+// Helicity spectra: from the unnormalised transforms of the packed real fields
+// V01 = v_x + i v_y, V2 = v_z, R01, R2 (v_reg), O01, O2 (omega), per k
+// Re(conj(v_k) . omega_k) and Re(conj(vreg_k) . omega_k) into shell round(|k|).
+template <class Real>
+__device__ __forceinline__ void unpack2(const void* F, long i, long m, double inv, double* ar, double* ai, double* br,
+                                        double* bi) {
+  const cplx<Real> z = ldc<Real>(F, i), zm = ldc<Real>(F, m);
+  *ar = 0.5 * ((double)z.x + zm.x) * inv;  *ai = 0.5 * ((double)z.y - zm.y) * inv;
+  *br = 0.5 * ((double)z.y + zm.y) * inv;  *bi = -0.5 * ((double)z.x - zm.x) * inv;
+}
+
+template <class Real>
+__global__ __launch_bounds__(64) void k_hel_spectral(const void* V01, const void* V2, const void* R01, const void* R2,
+                                                     const void* O01, const void* O2, int nx, int ny, int nz,
+                                                     int nshell, long chunk, double* __restrict__ bins_partial) {
+  extern __shared__ double bins[];            // [2][nshell]
+  for (int i = threadIdx.x; i < 2 * nshell; i += 64) bins[i] = 0.0;
+  __syncthreads();
+  const long n = (long)nx * ny * nz;
+  const double inv = 1.0 / (double)n;
+  const long i0 = (long)blockIdx.x * chunk;
+  const long i1 = (i0 + chunk < n) ? i0 + chunk : n;
+  for (long i = i0 + threadIdx.x; i < i1; i += 64) {
+    const int ix = (int)(i % nx), iy = (int)((i / nx) % ny), iz = (int)(i / ((long)nx * ny));
+    const long m = (long)((nz - iz) % nz) * nx * ny + (long)((ny - iy) % ny) * nx + (nx - ix) % nx;
+    double v[6], r[6], o[6], t0, t1;     // [x re, x im, y re, y im, z re, z im]
+    unpack2<Real>(V01, i, m, inv, &v[0], &v[1], &v[2], &v[3]);
+    unpack2<Real>(V2, i, m, inv, &v[4], &v[5], &t0, &t1);
+    unpack2<Real>(R01, i, m, inv, &r[0], &r[1], &r[2], &r[3]);
+    unpack2<Real>(R2, i, m, inv, &r[4], &r[5], &t0, &t1);
+    unpack2<Real>(O01, i, m, inv, &o[0], &o[1], &o[2], &o[3]);
+    unpack2<Real>(O2, i, m, inv, &o[4], &o[5], &t0, &t1);
+    double hv = 0.0, hr = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      hv += v[2 * a] * o[2 * a] + v[2 * a + 1] * o[2 * a + 1];
+      hr += r[2 * a] * o[2 * a] + r[2 * a + 1] * o[2 * a + 1];
+    }
+    const int kx = kfreq(ix, nx), ky = kfreq(iy, ny), kz = kfreq(iz, nz);
+    const int s = shell_of((long)kx * kx + (long)ky * ky + (long)kz * kz);
+    atomicAdd(&bins[s], hv);
+    atomicAdd(&bins[nshell + s], hr);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 2 * nshell; i += 64) bins_partial[(long)i * gridDim.x + blockIdx.x] = bins[i];
+}
+
 // ----------------------------------------------------------------- launch wrappers
 static unsigned grid_for(long n, int threads, unsigned cap = 4096) {
   long g = (n + threads - 1) / threads;
@@ -707,6 +888,44 @@ void launch_mach_partials(int prec, const void* psi, const void* d0, const void*
   else
     hipLaunchKernelGGL(k_mach_partials<float>, dim3(blocks), dim3(256), 0, st, psi, d0, d1, d2, (unsigned)n, alpha, psum, pmax);
 }
+#define GPK_PREC_LAUNCH(K, GRID, BLOCK, SH, ST, ...)                                   \
+  do {                                                                                 \
+    if (prec == P_C128) hipLaunchKernelGGL(K<double>, GRID, BLOCK, SH, ST, __VA_ARGS__); \
+    else hipLaunchKernelGGL(K<float>, GRID, BLOCK, SH, ST, __VA_ARGS__);               \
+  } while (0)
+void launch_hel_pack(int prec, const void* psi, const void* d0, const void* d1, const void* d2, void* s3, void* s4,
+                     void* s5, long n, double alpha, double* partial, unsigned blocks, hipStream_t st) {
+  GPK_PREC_LAUNCH(k_hel_pack, dim3(blocks), dim3(256), 0, st, psi, d0, d1, d2, s3, s4, s5, (unsigned)n, alpha,
+                  partial);
+}
+void launch_hel_omega(int prec, const void* t3, const void* t4, const void* t5, void* s6, void* s7, long n,
+                      hipStream_t st) {
+  GPK_PREC_LAUNCH(k_hel_omega, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, t3, t4, t5, s6, s7, (unsigned)n);
+}
+void launch_hel_acc(int prec, const void* H, const void* F1, int t1, const void* F2, int t2, int first, void* J0,
+                    void* J1, long n, hipStream_t st) {
+  GPK_PREC_LAUNCH(k_hel_acc, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, H, F1, t1, F2, t2, first, J0, J1,
+                  (unsigned)n);
+}
+void launch_hel_vreg(int prec, const void* psi, const void* d0, const void* d1, const void* d2, const void* j01,
+                     const void* j2, const void* w01, const void* w2, void* s3, void* s4, long n, double alpha,
+                     const double* g2_sum, double* partial, unsigned blocks, hipStream_t st) {
+  GPK_PREC_LAUNCH(k_hel_vreg, dim3(blocks), dim3(256), 0, st, psi, d0, d1, d2, j01, j2, w01, w2, s3, s4,
+                  (unsigned)n, alpha, g2_sum, partial);
+}
+void launch_hel_vpack(int prec, const void* psi, void* d0, void* d1, const void* d2, long n, double alpha,
+                      hipStream_t st) {
+  GPK_PREC_LAUNCH(k_hel_vpack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, psi, d0, d1, d2, (unsigned)n,
+                  alpha);
+}
+void launch_hel_spectral(int prec, const void* V01, const void* V2, const void* R01, const void* R2, const void* O01,
+                         const void* O2, int nx, int ny, int nz, int nshell, unsigned blocks, long chunk,
+                         double* bins, hipStream_t st) {
+  const size_t sh = sizeof(double) * 2 * (size_t)nshell;
+  GPK_PREC_LAUNCH(k_hel_spectral, dim3(blocks), dim3(64), sh, st, V01, V2, R01, R2, O01, O2, nx, ny, nz, nshell,
+                  chunk, bins);
+}
+#undef GPK_PREC_LAUNCH
 void launch_segmax(const double* in, long len, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_segmax, dim3(1), dim3(256), 0, st, in, len, out);
 }

@@ -934,6 +934,82 @@ gp_status gp_mach(gp_plan_t* p, const void* psi, void* work, double* out) {
   return GP_OK;
 }
 
+// out = d/dx_a in (spectral first derivative, Nyquist entry 0); in == out allowed
+static gp_status deriv_pass(gp_plan_s* p, int a, const void* in, void* out) {
+  if (p->ax[a].n == 1) {
+    HIPCHK(p, hipMemsetAsync(out, 0, p->ntot * p->S, p->stream));
+    return GP_OK;
+  }
+  return pass(p, a, V_PROP, in, out, p->ax[a].deriv, 0.0, nullptr, 1.0);
+}
+
+size_t gp_helicity_work_bytes(const gp_plan_t* p) {
+  if (!p || p->is_batch) return 0;
+  return 8 * p->ntot * p->S;
+}
+
+gp_status gp_helicity(gp_plan_t* p, const void* psi, void* work, double* out, double* spec, int32_t nshell) {
+  gp_status st = usable(p);
+  if (st != GP_OK) return st;
+  if (p->is_batch) return fail(GP_ERR_STATE, "batch plan: diagnostics run on single plans");
+  if (!psi || !work || !out) return fail(GP_ERR_ARG, "null argument");
+  if (spec && nshell != p->nshell) return fail(GP_ERR_ARG, "nshell %d != %d", nshell, p->nshell);
+  void* S[8];
+  for (int k = 0; k < 8; ++k) S[k] = field(p, work, k);
+  const long n = p->ntot;
+  const double al = p->d.alpha;
+  // S0..S2 = grad psi
+  if ((st = derivatives(p, psi, work, false)) != GP_OK) return st;
+  // vorticity: S3..S5 = packed velocity components, differentiated in place, then
+  // omega into S6 (x + i y) and S7 (z)
+  launch_hel_pack(p->prec, psi, S[0], S[1], S[2], S[3], S[4], S[5], n, al, p->loss_part, p->field_blocks, p->stream);
+  if ((st = check_launch(p)) != GP_OK) return st;
+  double* g2_sum = p->d_result + 2 + 2 * (size_t)p->nshell;          // sum |grad psi|^2 (floor of v_reg)
+  launch_segsum(p->loss_part, p->field_blocks, 1, g2_sum, p->stream);
+  if ((st = deriv_pass(p, 1, S[3], S[3])) != GP_OK) return st;
+  if ((st = deriv_pass(p, 2, S[4], S[4])) != GP_OK) return st;
+  if ((st = deriv_pass(p, 0, S[5], S[5])) != GP_OK) return st;
+  launch_hel_omega(p->prec, S[3], S[4], S[5], S[6], S[7], n, p->stream);
+  if ((st = check_launch(p)) != GP_OK) return st;
+  // J_i = Im(sum_j (d_i d_j psi)(d_j psi)*) into S4 (J_x + i J_y), S5 (J_z), one Hessian
+  // entry at a time in S3: H_ij = d_i (d_j psi)
+  struct Entry { int i, j; };
+  const Entry hess[6] = {{0, 0}, {1, 1}, {2, 2}, {1, 0}, {2, 0}, {2, 1}};
+  for (int e = 0; e < 6; ++e) {
+    const int i = hess[e].i, j = hess[e].j;
+    if ((st = deriv_pass(p, i, S[j], S[3])) != GP_OK) return st;
+    // H_ij adds conj(d_j psi) H_ij to J_i and, off the diagonal, conj(d_i psi) H_ij to J_j
+    launch_hel_acc(p->prec, S[3], S[j], i, i != j ? S[i] : S[j], i != j ? j : -1, e == 0, S[4], S[5], n, p->stream);
+    if ((st = check_launch(p)) != GP_OK) return st;
+  }
+  // v_reg into S3 (x + i y), S4 (z); physical-space sums of v.omega and v_reg.omega
+  launch_hel_vreg(p->prec, psi, S[0], S[1], S[2], S[4], S[5], S[6], S[7], S[3], S[4], n, al, g2_sum,
+                  p->field_part, p->field_blocks, p->stream);
+  if ((st = check_launch(p)) != GP_OK) return st;
+  launch_segsum(p->field_part, p->field_blocks, 2, p->d_result, p->stream);
+  if ((st = check_launch(p)) != GP_OK) return st;
+  if (spec) {
+    // spectra: v into S0 (x + i y), S1 (z); transforms of v, v_reg, omega; shell bins
+    launch_hel_vpack(p->prec, psi, S[0], S[1], S[2], n, al, p->stream);
+    if ((st = check_launch(p)) != GP_OK) return st;
+    for (int k : {0, 1, 3, 4, 6, 7})
+      if ((st = fwd3_unnorm(p, S[k])) != GP_OK) return st;
+    launch_hel_spectral(p->prec, S[0], S[1], S[3], S[4], S[6], S[7], p->d.n[0], p->d.n[1], p->d.n[2], p->nshell,
+                        p->spec_blocks, p->spec_chunk, p->bins_part, p->stream);
+    if ((st = check_launch(p)) != GP_OK) return st;
+    launch_segsum(p->bins_part, p->spec_blocks, 2 * p->nshell, p->d_result + 2, p->stream);
+    if ((st = check_launch(p)) != GP_OK) return st;
+  }
+  const size_t cnt = 2 + (spec ? 2 * (size_t)p->nshell : 0);
+  HIPCHK(p, hipMemcpyAsync(p->h_result, p->d_result, cnt * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  out[0] = p->h_result[0] / (double)n;
+  out[1] = p->h_result[1] / (double)n;
+  if (spec) memcpy(spec, p->h_result + 2, 2 * (size_t)p->nshell * sizeof(double));
+  if (!std::isfinite(out[0]) || !std::isfinite(out[1])) return fail(GP_ERR_NONFINITE, "helicity is not finite");
+  return GP_OK;
+}
+
 // nsteps steps of the semi-implicit backward Euler scheme; work slots 0..2.  The
 // explicit part n overwrites d/dz in place (its only reader), which streams faster
 // than writing a separate field.

@@ -291,17 +291,53 @@ def test_taylor_green_256_preparation_and_run():
     assert dn < 1e-10 and c[10] / 1.5 < de < 1.5 * c[10]
 
 
-def test_abc_preparation_is_close_to_the_paper():
+@pytest.fixture(scope="module")
+def abc_a_prepared():
+    r = _golden("abc_argle_energies.txt")["ABC_aIT"]
+    n, alpha, beta, dtau, tau_f = int(r[0]), r[1], r[2], r[3], r[4]
+    return _prepare(n, alpha, beta, dtau, int(round(tau_f / dtau)), ic="abc")
+
+
+def test_abc_preparation_is_close_to_the_paper(abc_a_prepared):
     """ABC_aIT (128^3, alpha = 0.05, beta = 40, dtau = 4e-3, tau_f = 30 from the
     phase-only ansatz with v = v_ABC).  The paper stopped these runs before
     eq. crit1 was met, with eq. crit2 near 1e-3; the state at tau_f then depends on
     the path, so the check is closeness: E_kin^i, E_q, E_int within 1 %, E_kin^c
     (1e-3 of the total) within 10 %, and eq. crit2 at tau_f below 2e-3."""
     r = _golden("abc_argle_energies.txt")["ABC_aIT"]
-    n, alpha, beta, dtau, tau_f = int(r[0]), r[1], r[2], r[3], r[4]
     g = dict(e_kin_i=r[5], e_kin_c=r[6], e_q=r[7], e_int=r[8])
-    _, e, rep = _prepare(n, alpha, beta, dtau, int(round(tau_f / dtau)), ic="abc")
+    _, e, rep = abc_a_prepared
     rel = _rels(e, g, keys=tuple(g))
     print("ABC_aIT:", {k: (e[k], g[k]) for k in rel}, "relative differences:", rel, "last step:", rep)
     assert rel["e_kin_i"] < 1e-2 and rel["e_q"] < 1e-2 and rel["e_int"] < 1e-2 and rel["e_kin_c"] < 0.1
     assert rep["crit_energy"] < 2e-3
+
+
+def test_helicity_of_the_prepared_fields(tg_a_prepared, abc_a_prepared):
+    """H and H_reg of the prepared fields against the paper's tables: the Taylor-Green
+    state has none (printed 1.4e-13 and -1.9e-11; its symmetries cancel every
+    contribution), the ABC state carries the helicity of the driving flow (printed
+    H = 2.41, H_reg = 2.47 for ABC_aIT; the classical value is 3).  The ABC state is
+    the not-converged preparation above (energies within 1 %).  H_reg, the quantity
+    the paper builds for this purpose, agrees to 1 % (measured 0.3 %); the plain H
+    samples v where it is singular (the paper calls it the noisier of the two) and
+    is checked to 15 % (measured 10 %).  Also the GPU against the oracle on the same
+    128^3 ABC field."""
+    from oracle import helicity as OH
+    import paper_2003_03590_amd as gp
+    phi_tg, _, _ = tg_a_prepared
+    w = I.WORKLOADS["tg128_argle"]
+    plan = gp.Plan(w["n"], w["alpha"], w["beta"], 1e-3, "c128")
+    H, Hreg, _ = plan.helicity(phi_tg)
+    plan.close()
+    print("TG_aIT helicity:", H, Hreg)
+    assert abs(H) < 1e-8 and abs(Hreg) < 1e-8
+    r = _golden("abc_argle_energies.txt")["ABC_aIT"]
+    phi_abc, _, _ = abc_a_prepared
+    plan = gp.Plan(int(r[0]), r[1], r[2], 1e-3, "c128")
+    H, Hreg, spec = plan.helicity(phi_abc)
+    plan.close()
+    print("ABC_aIT helicity:", H, Hreg, "printed", r[9], r[10])
+    assert abs(Hreg - r[10]) < 0.01 * r[10] and abs(H - r[9]) < 0.15 * r[9]
+    ref = OH.helicity(phi_abc.cpu().numpy(), r[1])
+    assert abs(H - ref["H"]) < 1e-9 * abs(ref["H"]) and abs(Hreg - ref["H_reg"]) < 1e-9 * abs(ref["H_reg"])

@@ -1,5 +1,6 @@
 """Velocity statistics on the GPU against the oracle: longitudinal velocity
-structure functions per axis (eq. strfunc-def) and Mach numbers (eq. Mach-Number)."""
+structure functions per axis (eq. strfunc-def), Mach numbers (eq. Mach-Number),
+helicity and regularized helicity with their spectra (eq. helicity, eq. Hreg)."""
 import math
 
 import numpy as np
@@ -7,6 +8,7 @@ import pytest
 
 import gp_inputs as I
 from oracle import gp as O
+from oracle import helicity as OH
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -94,4 +96,46 @@ def test_velocity_statistics_errors():
     plan = _plan(16, 0.3, 2.0, "c128")
     with pytest.raises(gp._lib.GPError):
         plan.structure_fn_velocity(_dev(I.random_field(16, seed=1), "c128"), p_order=3)
+    plan.close()
+
+
+def _hel_fields():
+    n = 16
+    x = 2 * np.pi * (np.arange(n) + 0.5) / n          # cores between grid points
+    X, Y, Z = x[None, None, :], x[None, :, None], x[:, None, None]
+    return {
+        "random12": I.random_field(12, seed=43),
+        "ragged": I.random_field((8, 12, 16), seed=44),     # (nz, ny, nx)
+        "tg32": I.tg_psi(32, 0.05, 1),
+        "lines16": (np.sin(X) + 1j * np.sin(Y)) * np.exp(2j * Z) * np.ones((n, n, n)),
+    }
+
+
+def _hel_scale(psi, alpha):
+    """mean |v| |omega|: the size of the terms whose mean is H."""
+    v = O.velocity(psi, alpha)
+    om = OH.curl(v)
+    return float(np.mean(np.sqrt(sum(c * c for c in v)) * np.sqrt(sum(c * c for c in om))))
+
+
+@pytest.mark.parametrize("name", ["random12", "ragged", "tg32", "lines16"])
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_helicity_matches_oracle(name, prec):
+    import paper_2003_03590_amd as gp
+    psi = _hel_fields()[name]
+    nz, ny, nx = psi.shape
+    alpha, beta = 0.3, 2.0
+    base = psi.astype(np.complex64).astype(np.complex128) if prec == "c64" else psi
+    ref = OH.helicity(base, alpha)
+    scale = _hel_scale(base, alpha)
+    plan = gp.Plan((nx, ny, nz), alpha, beta, 1e-3, prec)
+    H, Hreg, spec = plan.helicity(_dev(psi, prec))
+    # complex64: v and v_reg divide by |psi|^2 and |grad psi|^2, which amplifies the
+    # FP32 rounding of the derivatives near cores and stagnation points
+    tol = 1e-10 if prec == "c128" else 1e-3
+    print(name, prec, "H", H, ref["H"], "H_reg", Hreg, ref["H_reg"], "scale", scale)
+    assert abs(H - ref["H"]) < tol * scale and abs(Hreg - ref["H_reg"]) < tol * scale
+    assert np.abs(spec - ref["spec"]).max() < tol * scale
+    pt = 1e-9 if prec == "c128" else 1e-6        # spectra from FP32 transforms for complex64
+    assert abs(spec[0].sum() - H) < pt * scale and abs(spec[1].sum() - Hreg) < pt * scale
     plan.close()

@@ -80,3 +80,14 @@ def test_helicity_is_a_pseudoscalar():
         assert abs(rc[key] - r[key]) < 1e-10 * abs(r["H"]) + 1e-12
     assert abs(r["spec"][0].sum() - r["H"]) < 1e-10 * abs(r["H"])
     assert abs(r["spec"][1].sum() - r["H_reg"]) < 1e-9 * max(abs(r["H_reg"]), 1e-6)
+
+
+def test_taylor_green_ansatz_has_no_helicity():
+    """The Taylor-Green ansatz is mirror-symmetric about the planes of the flow's
+    symmetries, so H = H_reg = 0 (the paper prints 1e-13 and -2e-11 for the prepared
+    TG_aIT state).  Its critical points lie exactly on grid points; the floor on
+    |grad psi|^2 keeps v_reg finite there."""
+    for n, xi, e in ((32, 0.05, 1), (32, 0.1, 2)):
+        r = Hh.helicity(I.tg_psi(n, xi, e), 0.3)
+        assert abs(r["H"]) < 1e-12 and abs(r["H_reg"]) < 1e-12
+        assert np.abs(r["spec"]).max() < 1e-10
