@@ -14,6 +14,13 @@ Initial conditions follow the paper's "Initial data preparation" section:
   lexicographic (kz, ky, kx) order draw a, b ~ N(0, 1) and set
   theta_hat_k = a + i b (folded mod N); Hermitian-symmetrise, zero the mean
   mode, transform to real space and scale to rms(theta) = 1.  psi = exp(i theta).
+* ``srp_spline_theta`` -- the paper's own smoothed random phase: theta uniform in
+  [-K, K] at N_r^3 control points (spacing N_s = N / N_r grid points), drawn with
+  numpy PCG64(seed) as one (N_r, N_r, N_r) array in [z][y][x] order, then a
+  periodic uniform cubic spline along x, y and z in turn (second derivatives from
+  the cyclic tridiagonal system N_s^2 (M_{i-1} + 4 M_i + M_{i+1}) =
+  6 (c_{i-1} - 2 c_i + c_{i+1}) over neighbouring control points; values between
+  them from the A, B, C, D weights of the SRP section).
 * ``tg_psi`` -- Taylor-Green ansatz: Clebsch potentials (eq. clebsch3d),
   psi_e (eq. psie, tanh argument read as r / (sqrt(2) xi)), the product of
   four shifted copies (eq. psi4) raised to [1/(2 pi alpha)] (eq. psitot3d),
@@ -37,7 +44,7 @@ import math
 import numpy as np
 
 __all__ = [
-    "grid", "srp_fourier_theta", "srp_mode_count", "tg_psi", "tg_velocity", "abc_velocity", "abc_psi",
+    "grid", "srp_fourier_theta", "srp_mode_count", "srp_spline_theta", "tg_psi", "tg_velocity", "abc_velocity", "abc_psi",
     "ABC_COEFFS", "pade_f",
     "PADE_A1", "PADE_A2", "PADE_B1", "rvr_psi", "rvr_draws", "random_field",
     "random_real", "alpha_beta_from_xi", "alpha_beta_table1", "WORKLOADS",
@@ -94,6 +101,42 @@ def tg_velocity(n: int):
     vz = np.zeros((n, n, n))
     return [vz, np.ascontiguousarray(np.broadcast_to(vy, (n, n, n))),
             np.ascontiguousarray(np.broadcast_to(vx, (n, n, n)))]
+
+
+def _spline_axis(c, ns: int, axis: int):
+    """Periodic uniform cubic spline along `axis` of control values c (spacing ns grid
+    points): returns the values at all ns * len grid points of that axis."""
+    c = np.moveaxis(np.asarray(c, dtype=np.float64), axis, 0)
+    nr = c.shape[0]
+    # cyclic tridiagonal system for the second derivatives M at the control points
+    a = np.zeros((nr, nr))
+    for i in range(nr):
+        a[i, i] += 4.0
+        a[i, (i - 1) % nr] += 1.0
+        a[i, (i + 1) % nr] += 1.0
+    rhs = 6.0 * (np.roll(c, 1, axis=0) - 2.0 * c + np.roll(c, -1, axis=0)) / (ns * ns)
+    m = np.tensordot(np.linalg.inv(a), rhs, axes=(1, 0))
+    out = np.empty((nr * ns,) + c.shape[1:])
+    for s in range(ns):
+        A = (ns - s) / ns
+        B = s / ns
+        C = (A ** 3 - A) * ns * ns / 6.0
+        D = (B ** 3 - B) * ns * ns / 6.0
+        out[s::ns] = A * c + B * np.roll(c, -1, axis=0) + C * m + D * np.roll(m, -1, axis=0)
+    return np.moveaxis(out, 0, axis)
+
+
+def srp_spline_theta(n: int, K: float, nr: int, seed: int) -> np.ndarray:
+    """The SRP phase of the paper (SRP section): uniform random values in [-K, K] at
+    nr^3 control points, periodic cubic spline interpolation along each axis; n must
+    be a multiple of nr.  Returns theta [z][y][x] (FP64)."""
+    if n % nr:
+        raise ValueError("n must be a multiple of nr")
+    ns = n // nr
+    c = np.random.default_rng(seed).uniform(-K, K, (nr, nr, nr))
+    for axis in (2, 1, 0):                      # x, then y, then z
+        c = _spline_axis(c, ns, axis)
+    return c
 
 
 ABC_COEFFS = (0.9 / math.sqrt(3.0), 1.0 / math.sqrt(3.0), 1.1 / math.sqrt(3.0))   # (A, B, C)
@@ -268,6 +311,13 @@ WORKLOADS = {
     # alpha = 0.05, beta = 40 (parameter-table rule), dtau = 4e-3, tau_f = 30
     "abc128_argle": dict(n=128, prec=("c128",), alpha=0.05, beta=40.0, dtau=4e-3, steps=7500,
                          ic=("abc", {}), velocity="abc"),
+    # paper-size ensembles of the SRP and RVR benchmarks at 128^3 (runs SRP_a and
+    # RVR_a of their parameter tables; alpha, beta from the parameter-table rule);
+    # ten seeds each, as the paper's ensemble averages
+    "srp128_paper": dict(n=128, prec=("c128",), alpha=0.05, beta=40.0, dt=1.0 / 1024, t_final=8.0,
+                         K=8 * math.pi, nr=4, seeds=tuple(range(10))),
+    "rvr128_paper": dict(n=128, prec=("c128",), alpha=0.05, beta=40.0, dt=1.0 / 1024, t_final=8.0,
+                         n_pairs=200, R=math.pi / 2, seeds=tuple(range(10))),
     "ens48": dict(runs=[dict(n=64, alpha=0.1, beta=20.0, seed=100 + i) for i in range(32)]
                   + [dict(n=96, alpha=6.4 / 96, beta=30.0, seed=132 + i) for i in range(16)],
                   prec=("c64",), dt=1e-3, steps=300, K=4, diag_every=50),

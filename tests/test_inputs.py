@@ -62,3 +62,39 @@ def test_workload_parameters():
     w3 = I.WORKLOADS["rvr1024"]
     assert abs(w3["alpha"] - 0.0260325) < 1e-6 and abs(w3["beta"] - 76.82699) < 1e-4
     assert len(I.WORKLOADS["ens48"]["runs"]) == 48
+
+
+def test_srp_spline_matches_the_periodic_cubic_spline_of_scipy():
+    """The paper's spline SRP (SRP section) is the periodic uniform cubic spline
+    through the control values, axis by axis: scipy's CubicSpline with periodic end
+    conditions gives the same values on 1-D lines and, applied along each axis in
+    turn, on the whole grid; the control values are reproduced exactly."""
+    from scipy.interpolate import CubicSpline
+    import gp_inputs as I
+    n, nr, K = 32, 4, 8 * np.pi
+    ns = n // nr
+    th = I.srp_spline_theta(n, K, nr, seed=3)
+    c = np.random.default_rng(3).uniform(-K, K, (nr, nr, nr))
+    assert np.abs(th[::ns, ::ns, ::ns] - c).max() < 1e-12
+    assert np.abs(th).max() <= 2 * K
+    knots = np.arange(nr + 1) * ns
+    fine = np.arange(n)
+    ref = c
+    for axis in (2, 1, 0):
+        ext = np.concatenate([ref, np.take(ref, [0], axis=axis)], axis=axis)
+        ref = CubicSpline(knots, ext, axis=axis, bc_type="periodic")(fine)
+    assert np.abs(th - ref).max() < 1e-10 * K
+    # a single line is C2 and periodic: second differences change smoothly across the wrap
+    line = th[0, 0, :]
+    d2 = np.roll(line, -1) - 2 * line + np.roll(line, 1)
+    assert np.abs(np.diff(np.concatenate([d2, d2[:1]]))).max() < 0.5 * np.abs(d2).max()
+
+
+def test_srp_spline_rejects_bad_sizes_and_is_seeded():
+    import gp_inputs as I
+    import pytest as _pt
+    with _pt.raises(ValueError):
+        I.srp_spline_theta(30, 1.0, 4, 0)
+    a = I.srp_spline_theta(16, 1.0, 4, 5)
+    assert np.array_equal(a, I.srp_spline_theta(16, 1.0, 4, 5))
+    assert not np.array_equal(a, I.srp_spline_theta(16, 1.0, 4, 6))
