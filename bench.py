@@ -346,7 +346,7 @@ def main(argv=None):
                      "kernel": "axis_pass (x: fused nonlinear + propagator, y, z: propagator), mean of the three",
                      "per_launch_bytes": bytes_per_pass, "mean_launch_us": f64["mean_pass_ms"] * 1e3},
         "drift_f64": {"dE": f64["dE"], "dN": f64["dN"]},
-        "schedule": [f64["plan"].schedule(ax) for ax in range(3)],
+        "schedule": [f64["plan"].schedule(ax) for ax in range(5)],
     }
     if not a.no_fp32:
         f32 = run_form(gp, torch, psi0, w, "c64", a.steps, a.warmup, tune=not a.no_tune)
@@ -358,7 +358,7 @@ def main(argv=None):
                        "dE": f32["dE"], "dN": f32["dN"], "rel_l2_psi_vs_f64_gpu": rel,
                        "axis_pass_gbs": ach32, "axis_pass_frac": ach32 / HBM_PEAK_GBS,
                        "mean_launch_us": f32["mean_pass_ms"] * 1e3,
-                       "schedule": [f32["plan"].schedule(ax) for ax in range(3)]}
+                       "schedule": [f32["plan"].schedule(ax) for ax in range(5)]}
     if not a.no_ensemble:
         res["ensemble"] = ensemble_form(gp, torch, I)
     if not a.no_large:

@@ -261,7 +261,8 @@ GP_API gp_status gp_energies_batch(gp_plan_t* p, void* const* psis, void* work, 
 GP_API const char* gp_last_error(void);
 
 /* Name of the compiled FFT schedule used for an axis, e.g. "N=256 T=16 W=8 R=16x16".
- * axis 3 names the xy choice: "xy: separate passes" or "xy: plane N=.. T=..". */
+ * axis 3 names the xy choice: "xy: separate passes" or "xy: plane N=.. T=..";
+ * axis 4 the pass that carries the nonlinear rotation ("nl: x pass", ...). */
 GP_API const char* gp_schedule_name(const gp_plan_t* p, int32_t axis);
 
 /* Number of compiled schedule variants for an axis length and precision, and
@@ -272,7 +273,11 @@ GP_API const char* gp_schedule_name(const gp_plan_t* p, int32_t axis);
  * z-plane (both sub-steps on chip, psi read and written once; the x and y factors
  * commute, time-evolution section).  Variant 1 needs nx == ny with a compiled
  * plane length (complex64: 16..96, complex128: 16..64); otherwise
- * GP_ERR_UNSUPPORTED. */
+ * GP_ERR_UNSUPPORTED.  axis 4 (single plans, separate passes) selects the axis pass
+ * that carries the nonlinear rotation as its prologue and runs first in each
+ * linear step (variant 0, 1, 2 = x, y, z; the linear sub-steps commute, so any
+ * order is the same split step); default: the first axis of length > 1.  Batch
+ * plans: GP_ERR_STATE for every axis but 3. */
 GP_API int32_t gp_variant_count(int32_t n, int32_t prec);
 GP_API gp_status gp_select_variant(gp_plan_t* p, int32_t axis, int32_t variant);
 
@@ -280,7 +285,9 @@ GP_API gp_status gp_select_variant(gp_plan_t* p, int32_t axis, int32_t variant);
  * time `reps` launches of each compiled schedule variant on `scratch` (dev, one
  * state of the plan's largest run; its contents are overwritten) with HIP
  * events, and keep the fastest; then the xy choice (axis 3), timed with as many
- * runs per launch as the size group holds.  cache_path (may be NULL): a JSON file of
+ * runs per launch as the size group holds; then, for single plans with separate
+ * passes, the nonlinear carrier (axis 4), timed as whole linear steps.  cache_path
+ * (may be NULL): a JSON file of
  * earlier choices keyed by GPU architecture, precision, grid shape and axis;
  * cached choices are applied without timing and new ones are added.
  * Synchronizes.  A batch plan re-records its graph on the next step call. */

@@ -117,7 +117,7 @@ class Plan:
         scratch = _torch().zeros(self.shape, dtype=self.dtype, device=self.device)
         _check(lib().gp_autotune(self._h, C.c_void_p(_ptr(scratch)), int(reps),
                                  cache.encode() if cache else None))
-        return [self.schedule(a) for a in range(4)]
+        return [self.schedule(a) for a in range(5)]
 
     # ---------------------------------------------------------------- method
     def init_phase(self, theta, out=None):

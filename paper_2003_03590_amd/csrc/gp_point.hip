@@ -766,6 +766,13 @@ __global__ __launch_bounds__(64) void k_hel_spectral(const void* V01, const void
   for (int i = threadIdx.x; i < 2 * nshell; i += 64) bins_partial[(long)i * gridDim.x + blockIdx.x] = bins[i];
 }
 
+// every point <- (re, im)
+template <class Real>
+__global__ __launch_bounds__(256) void k_fill(void* f, unsigned n, double re, double im) {
+  const unsigned i = blockIdx.x * 256u + threadIdx.x;
+  if (i < n) stc<Real>(f, i, re, im);
+}
+
 // ----------------------------------------------------------------- launch wrappers
 static unsigned grid_for(long n, int threads, unsigned cap = 4096) {
   long g = (n + threads - 1) / threads;
@@ -926,6 +933,10 @@ void launch_hel_spectral(int prec, const void* V01, const void* V2, const void* 
                   chunk, bins);
 }
 #undef GPK_PREC_LAUNCH
+void launch_fill(int prec, void* f, long n, double re, double im, hipStream_t st) {
+  if (prec == P_C128) hipLaunchKernelGGL(k_fill<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, f, (unsigned)n, re, im);
+  else hipLaunchKernelGGL(k_fill<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, f, (unsigned)n, re, im);
+}
 void launch_segmax(const double* in, long len, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_segmax, dim3(1), dim3(256), 0, st, in, len, out);
 }

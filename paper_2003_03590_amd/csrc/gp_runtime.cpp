@@ -168,7 +168,8 @@ struct gp_plan_s {
   double* h_result = nullptr;      // pinned mirror
   bool broken = false;
   bool own_stream = false;         // stream created by the plan (batch plans on the null stream)
-  std::string sched_name[4];       // x, y, z axis schedules; [3]: the xy-plane choice
+  std::string sched_name[5];       // x, y, z axis schedules; [3]: the xy-plane choice; [4]: the nonlinear carrier
+  int nl_axis = -1;                // axis pass that carries the nonlinear prologue (-1: first real axis)
   // xy-plane pass (x and y sub-steps fused; needs nx == ny with a compiled plane schedule)
   struct Plane {
     const PlaneEntry* e = nullptr;
@@ -384,6 +385,7 @@ gp_status plan_init(gp_plan_s* p, const gp_desc* d, hipStream_t stream) {
   }
   p->plane.e = (d->n[0] == d->n[1] && d->n[0] > 1) ? find_plane(d->n[0], p->prec) : nullptr;
   p->sched_name[3] = "xy: separate passes";
+  p->sched_name[4] = "nl: first axis";
   // reduction partials
   const long kin_n = (long)p->ax[0].blocks + p->ax[1].blocks + p->ax[2].blocks;
   if ((st = dev_alloc(p, (void**)&p->kin_part, std::max(1L, kin_n) * sizeof(double))) != GP_OK) return st;
@@ -486,9 +488,14 @@ gp_status linear_all(gp_plan_s* p, void* psi, int tau, bool with_nl, double nl) 
     if ((st = check_launch(p)) != GP_OK) return st;
     return p->ax[2].n > 1 ? pass(p, 2, V_PROP, psi, psi, p->ax[2].mult[tau]) : GP_OK;
   }
-  for (int a = 0; a < 3; ++a) {
+  // the linear sub-steps commute: the axis that carries the nonlinear prologue runs
+  // first, the others follow in x, y, z order
+  const int carrier = (p->nl_axis >= 0 && p->ax[p->nl_axis].n > 1) ? p->nl_axis : c;
+  const int order[3] = {carrier, carrier == 0 ? 1 : 0, carrier == 2 ? 1 : 2};
+  for (int q = 0; q < 3; ++q) {
+    const int a = order[q];
     if (p->ax[a].n == 1) continue;
-    const bool nl_here = with_nl && a == c;
+    const bool nl_here = with_nl && a == carrier;
     if ((st = pass(p, a, nl_here ? V_PROP_NL : V_PROP, psi, psi, p->ax[a].mult[tau], nl)) != GP_OK) return st;
   }
   return GP_OK;
@@ -654,7 +661,7 @@ int32_t gp_nshell(const gp_plan_t* p) { return p ? p->nshell : 0; }
 const char* gp_last_error(void) { return g_err.c_str(); }
 
 const char* gp_schedule_name(const gp_plan_t* p, int32_t axis) {
-  if (!p || axis < 0 || axis > 3) return "";
+  if (!p || axis < 0 || axis > 4) return "";
   return p->sched_name[axis].c_str();
 }
 
@@ -694,6 +701,13 @@ gp_status gp_select_variant(gp_plan_t* p, int32_t axis, int32_t variant) {
     snprintf(nm, sizeof nm, "xy: plane N=%d T=%d R=%dx%dx%d", p->plane.e->n, p->plane.e->T, p->plane.e->radix[0],
              p->plane.e->radix[1], p->plane.e->radix[2]);
     p->sched_name[3] = nm;
+    return GP_OK;
+  }
+  if (axis == 4) {   // which axis pass carries the nonlinear prologue: 0, 1, 2 = x, y, z
+    if (variant < 0 || variant > 2) return fail(GP_ERR_ARG, "nonlinear carrier %d (0, 1, 2 = x, y, z)", variant);
+    if (p->ax[variant].n == 1) return fail(GP_ERR_ARG, "nonlinear carrier: axis %d has length 1", variant);
+    p->nl_axis = variant;
+    p->sched_name[4] = std::string("nl: ") + "xyz"[variant] + " pass";
     return GP_OK;
   }
   if (axis < 0 || axis > 2) return fail(GP_ERR_ARG, "axis %d", axis);
@@ -1521,8 +1535,32 @@ static gp_status tune_xy(gp_plan_s* p, void* scratch, int reps, int runs, int* c
   return GP_OK;
 }
 
+// time the composed step L(dt) with the nonlinear prologue on each real axis in turn
+// (state: psi = 1, the small-angle rotation of every real run); keep the fastest
+static gp_status tune_nl(gp_plan_s* p, void* scratch, int reps, int* choice) {
+  gp_status st;
+  launch_fill(p->prec, scratch, p->ntot, 1.0, 0.0, p->stream);
+  if ((st = check_launch(p)) != GP_OK) return st;
+  const double nl = p->d.beta * p->d.dt;
+  double best = 1e300;
+  *choice = first_real_axis(p);
+  for (int a = 0; a < 3; ++a) {
+    if (p->ax[a].n == 1) continue;
+    p->nl_axis = a;
+    double us = 0;
+    gp_status inner = GP_OK;
+    if ((st = time_calls(p, reps, &us, [&] {
+           if (inner == GP_OK) inner = linear_all(p, scratch, TAU_DT, true, nl);
+         })) != GP_OK)
+      return st;
+    if (inner != GP_OK) return inner;
+    if (us < best) { best = us; *choice = a; }
+  }
+  return GP_OK;
+}
+
 static gp_status tune_plan(gp_plan_s* p, void* scratch, int reps, std::map<std::string, int>& cache,
-                           const std::string& arch, int chosen[4], int runs) {
+                           const std::string& arch, int chosen[5], int runs) {
   gp_status st;
   for (int a = 0; a < 3; ++a) {
     chosen[a] = 0;
@@ -1562,6 +1600,19 @@ static gp_status tune_plan(gp_plan_s* p, void* scratch, int reps, std::map<std::
     }
     if ((st = gp_select_variant(p, 3, chosen[3])) != GP_OK) return st;
   }
+  // single plans with separate passes: the axis that carries the nonlinear prologue
+  chosen[4] = first_real_axis(p);
+  if (runs == 1 && !p->plane.on && chosen[4] >= 0) {
+    const std::string key = tune_key(arch, p, 4);
+    auto it = cache.find(key);
+    if (it != cache.end() && it->second >= 0 && it->second <= 2 && p->ax[it->second].n > 1) {
+      chosen[4] = it->second;
+    } else {
+      if ((st = tune_nl(p, scratch, reps, &chosen[4])) != GP_OK) return st;
+      cache[key] = chosen[4];
+    }
+    if ((st = gp_select_variant(p, 4, chosen[4])) != GP_OK) return st;
+  }
   return GP_OK;
 }
 
@@ -1573,12 +1624,12 @@ gp_status gp_autotune(gp_plan_t* p, void* scratch, int32_t reps, const char* cac
   auto cache = read_cache(cache_path);
   const std::string arch = arch_name();
   if (!p->is_batch) {
-    int chosen[4];
+    int chosen[5];
     if ((st = tune_plan(p, scratch, reps, cache, arch, chosen, 1)) != GP_OK) return st;
   } else {
     for (auto& g : p->groups) {
       gp_plan_s* r0 = p->runs[g.members[0]];
-      int chosen[4];
+      int chosen[5];
       if ((st = tune_plan(r0, scratch, reps, cache, arch, chosen, (int)g.members.size())) != GP_OK) return st;
       for (size_t i = 1; i < g.members.size(); ++i)
         for (int a = 0; a < 4; ++a) {

@@ -384,9 +384,11 @@ def test_autotune_and_cache(tmp_path):
     plan = _plan(64, 0.3, 4.0, 0.01, "c64")
     chosen = plan.autotune(reps=2, cache=cache)
     data = json.load(open(cache))
-    # three axis schedules and the xy choice (plane pass or separate passes, single run)
-    assert len(data) == 4 and all(k.split("/")[1] == "c64" for k in data)
-    assert any(k.endswith("/a3/r1") for k in data) and len(chosen) == 4
+    # three axis schedules, the xy choice (plane pass or separate passes, single run)
+    # and, with separate passes, the axis that carries the nonlinear rotation
+    assert all(k.split("/")[1] == "c64" for k in data)
+    assert any(k.endswith("/a3/r1") for k in data) and len(chosen) == 5
+    assert len(data) == (5 if chosen[3].startswith("xy: separate") else 4)
     plan2 = _plan(64, 0.3, 4.0, 0.01, "c64")
     assert plan2.autotune(reps=2, cache=cache) == chosen
     psi0 = I.random_field(64, seed=77)
@@ -401,3 +403,30 @@ def test_autotune_and_cache(tmp_path):
     bp.autotune(reps=2, cache=cache)
     bp.step_n(sts, 1)
     assert len(json.load(open(cache))) >= 8
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_nonlinear_carrier_axis(prec):
+    """The nonlinear rotation may ride on any axis pass (the linear sub-steps commute):
+    every choice gives the oracle's split step; bad choices are rejected."""
+    import paper_2003_03590_amd as gp
+    shape = (24, 16, 12)
+    psi0 = I.random_field((12, 16, 24), seed=61)
+    base = psi0.astype(np.complex64).astype(np.complex128) if prec == "c64" else psi0
+    ref = O.evolve(base, 0.3, 4.0, 0.01, 5)
+    plan = gp.Plan(shape, 0.3, 4.0, 0.01, prec)
+    for carrier in (0, 1, 2):
+        plan.select_variant(4, carrier)
+        assert plan.schedule(4) == "nl: " + "xyz"[carrier] + " pass"
+        psi = _to_dev(psi0, prec)
+        plan.step_n(psi, 5)
+        assert rel_l2(psi.cpu().numpy(), ref) < (1e-12 if prec == "c128" else 2e-6)
+        plan.step_n(psi, -5)
+        assert rel_l2(psi.cpu().numpy(), base) < (1e-12 if prec == "c128" else 4e-6)
+    with pytest.raises(gp._lib.GPError):
+        plan.select_variant(4, 3)
+    plan.close()
+    flat = gp.Plan((16, 16, 1), 0.3, 4.0, 0.01, prec)
+    with pytest.raises(gp._lib.GPError):
+        flat.select_variant(4, 2)            # axis of length 1
+    flat.close()
