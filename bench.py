@@ -279,7 +279,6 @@ def main(argv=None):
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the 1024^3 complex64 HBM-bound form")
-    ap.add_argument("--no-argle", action="store_true", help="skip the 256^3 imaginary-time preparation form")
     ap.add_argument("--argle", action="store_true",
                     help="profiling mode: time only the 256^3 imaginary-time preparation, print its JSON, exit")
     ap.add_argument("--passes", default=None, metavar="N:PREC",
@@ -343,7 +342,8 @@ def main(argv=None):
         "bytes_per_split_step_min": 6.0 * npts * S,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": pass_traffic(),
-                     "kernel": "axis_pass (x: fused nonlinear + propagator, y, z: propagator), mean of the three",
+                     "kernel": "axis_pass (propagator; the nonlinear rotation fused into the carrier axis's pass), "
+                               "mean of the three",
                      "per_launch_bytes": bytes_per_pass, "mean_launch_us": f64["mean_pass_ms"] * 1e3},
         "drift_f64": {"dE": f64["dE"], "dN": f64["dN"]},
         "schedule": [f64["plan"].schedule(ax) for ax in range(5)],
@@ -363,8 +363,6 @@ def main(argv=None):
         res["ensemble"] = ensemble_form(gp, torch, I)
     if not a.no_large:
         res["large_1024_c64"] = large_form(gp, torch, I)
-    if not a.no_argle:
-        res["argle_256"] = argle_form(gp, torch, I)
     if not a.no_cpu_baseline:
         res["cpu_baseline"] = oracle_sample(psi0, w)
     print(json.dumps(res))

@@ -1,10 +1,12 @@
 // Pointwise and reduction kernels of the Gross-Pitaevskii library:
 // the initial phase field, the standalone nonlinear sub-step, the
 // hydrodynamic diagnostics (energy decomposition and shell spectra), the
-// spectral loss and its gradient, the phase gradient, and the density
-// structure function.  All reductions are deterministic: fixed-order wave
-// butterflies, per-workgroup partials, and a fixed-order final sum with
-// Neumaier compensation; shell bins are accumulated per wavefront in LDS.
+// imaginary-time (ARGLE) step and its energy, the spectral loss and its
+// gradient, the phase gradient, the density and velocity structure functions,
+// the Mach numbers and the helicities.  All reductions are deterministic:
+// fixed-order wave butterflies, per-workgroup partials, and a fixed-order final
+// sum with Neumaier compensation (maxima are order-free); shell bins are
+// accumulated per wavefront in LDS.
 #include "gp_point.h"
 
 namespace gpk {
@@ -54,9 +56,6 @@ __device__ __forceinline__ int shell_of(long k2) {
 }
 
 __device__ __forceinline__ int kfreq(int i, int n) { return (2 * i < n) ? i : i - n; }  // fftfreq (Nyquist -> -n/2)
-__device__ __forceinline__ int kfirst(int i, int n) {                                   // Nyquist zeroed
-  return (n % 2 == 0 && 2 * i == n) ? 0 : kfreq(i, n);
-}
 
 // ----------------------------------------------------------------- elementwise
 template <class Real>
