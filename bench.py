@@ -257,16 +257,25 @@ def passes_mode(gp, torch, spec, reps, tune=False, variants=None):
 
 
 def oracle_sample(psi0_np, w):
-    """The CPU oracle on a bounded sample: one literal Strang step of the same 256^3 field."""
+    """The CPU oracle on a bounded sample: one literal Strang step of the same 256^3 field;
+    beside it, seconds per step at 32^3 ... 128^3 (the same construction) for context."""
+    import gp_inputs as I
     from oracle import gp as O
     t = time.perf_counter()
     O.strang_step(psi0_np, w["alpha"], w["beta"], w["dt"])
     dt = time.perf_counter() - t
     npts = float(psi0_np.size)
+    sizes = {}
+    for n in (32, 64, 96, 128):
+        psi = I.tg_psi(n, w["ic"][1]["xi"], w["ic"][1]["exponent"])
+        t1 = time.perf_counter()
+        O.strang_step(psi, w["alpha"], w["beta"], w["dt"])
+        sizes[str(n)] = time.perf_counter() - t1
+    sizes["256"] = dt
     return {"value": npts / dt, "unit": "grid-point.steps/s", "cores": 1, "kind": "oracle",
             "sample": f"one literal Strang step (4 3-D FFTs, numpy FP64, single thread) of the 256^3 "
                       f"tg256 field, {dt:.1f} s on {cpu_model()}; diagnostics (1 per 100 steps) not included",
-            "seconds": dt, "host_cpus": os.cpu_count()}
+            "seconds": dt, "seconds_per_step_by_n": sizes, "host_cpus": os.cpu_count()}
 
 
 def main(argv=None):
