@@ -65,3 +65,29 @@ def test_every_supported_length_has_a_schedule():
     for n in (2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024):
         for prec in (0, 1):
             assert lib.gp_variant_count(n, prec) >= 1, (n, prec)
+
+
+@needs_lib
+def test_new_entry_points_reject_null_plans_without_gpu():
+    """Every entry point validates its arguments on the host before any GPU work:
+    a null plan is GP_ERR_ARG with a message, for the imaginary-time, velocity
+    statistics and helicity calls as for the rest."""
+    import paper_2003_03590_amd as gp
+    from paper_2003_03590_amd import _lib
+    lib = gp.lib()
+    d = C.c_double()
+    two = (C.c_double * 2)()
+    rep = _lib.gp_argle_report()
+    calls = [
+        lambda: lib.gp_argle_step(None, None, None, 0.01, 1, None),
+        lambda: lib.gp_argle_energy(None, None, None, None, C.byref(d)),
+        lambda: lib.gp_argle_run(None, None, None, 0.01, 10, 5, 0.0, None, C.byref(rep)),
+        lambda: lib.gp_structure_fn_velocity(None, None, None, 2, two, None),
+        lambda: lib.gp_mach(None, None, None, two),
+        lambda: lib.gp_helicity(None, None, None, two, None, 0),
+    ]
+    for f in calls:
+        assert f() == _lib.GP_ERR_ARG
+        assert lib.gp_last_error().decode()
+    assert lib.gp_helicity_work_bytes(None) == 0
+    assert lib.gp_schedule_name(None, 4) == b""
