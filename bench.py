@@ -299,7 +299,7 @@ def main(argv=None):
                     help="with --passes: schedule variant of each axis (as reported by a timed run)")
     a = ap.parse_args(argv)
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU "
+        print(f"bench.py: runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU "
               "decomposition is a design, not a built path", file=sys.stderr)
         return 2
 
