@@ -341,3 +341,23 @@ def test_helicity_of_the_prepared_fields(tg_a_prepared, abc_a_prepared):
     assert abs(Hreg - r[10]) < 0.01 * r[10] and abs(H - r[9]) < 0.15 * r[9]
     ref = OH.helicity(phi_abc.cpu().numpy(), r[1])
     assert abs(H - ref["H"]) < 1e-9 * abs(ref["H"]) and abs(Hreg - ref["H_reg"]) < 1e-9 * abs(ref["H_reg"])
+
+
+@pytest.mark.parametrize("shape", [(16, 12, 1), (1, 16, 8), (32, 1, 1)], ids=lambda s: "x".join(map(str, s)))
+def test_argle_on_degenerate_grids(shape):
+    """Grids with axes of length 1 (2-D and 1-D problems): that axis has only k = 0,
+    so its derivative vanishes; steps, E_v and the stopping rule match the oracle."""
+    nx, ny, nz = shape
+    alpha, beta, dtau = 0.2, 5.0, 0.02
+    phi0 = I.random_field((nz, ny, nx), seed=35)
+    rng = np.random.default_rng(36)
+    v = [0.3 * rng.standard_normal((nz, ny, nx)) for _ in range(3)]
+    plan = _plan(shape, alpha, beta)
+    vd = _to_dev_v(v, "c128")
+    phi = _to_dev(phi0, "c128")
+    r = plan.argle_run(phi, vd, dtau, 9, check_every=4, eps=0.0)
+    ref, steps, cs, ce, ev, conv = A.argle_run(phi0, v, alpha, beta, dtau, 9, 4, 0.0)
+    assert r["steps"] == steps and abs(r["e_v"] - ev) < 1e-12 * ev
+    assert abs(r["crit_sup"] - cs) < 1e-10 * cs
+    assert _rel(phi.cpu().numpy(), ref) < 1e-12
+    plan.close()

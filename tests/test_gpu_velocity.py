@@ -139,3 +139,21 @@ def test_helicity_matches_oracle(name, prec):
     pt = 1e-9 if prec == "c128" else 1e-6        # spectra from FP32 transforms for complex64
     assert abs(spec[0].sum() - H) < pt * scale and abs(spec[1].sum() - Hreg) < pt * scale
     plan.close()
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_helicity_of_a_planar_flow_vanishes(prec):
+    """On a 2-D grid (nz = 1) v lies in the plane and omega = curl v is normal to it,
+    so H = H_reg = 0 (the oracle to round-off).  complex128 likewise; complex64
+    carries two real velocity components per transform, and FP32 rounding leaks
+    ~1e-7 of one into the other, so it is zero to ~1e-6 of <|v||omega|>."""
+    import paper_2003_03590_amd as gp
+    psi = I.random_field((1, 16, 24), seed=45)
+    ref = OH.helicity(psi, 0.3)
+    scale = _hel_scale(psi, 0.3)
+    plan = gp.Plan((24, 16, 1), 0.3, 2.0, 1e-3, prec)
+    H, Hreg, spec = plan.helicity(_dev(psi, prec))
+    assert abs(ref["H"]) < 1e-14 * scale and abs(ref["H_reg"]) < 1e-14 * scale
+    tol = (1e-13 if prec == "c128" else 1e-6) * scale
+    assert abs(H) < tol and abs(Hreg) < tol and np.abs(spec).max() < tol
+    plan.close()
