@@ -1,6 +1,7 @@
-"""The paper's 512^3 Taylor-Green and ABC preparations and runs (TG_cIT + TG_c,
-ABC_cIT) against its printed tables.  Each takes minutes on one GPU, so they run
-only on request: set GP_PAPER512=1 (they are skipped otherwise)."""
+"""The paper's 512^3 runs: the Taylor-Green and ABC preparations (TG_cIT + TG_c,
+ABC_cIT) against its printed tables, and one run each of the SRP and RVR
+benchmarks (SRP_c, RVR_c) against the behaviour it describes.  Each takes minutes
+on one GPU, so they run only on request: set GP_PAPER512=1 (skipped otherwise)."""
 import math
 import os
 import time
@@ -113,3 +114,57 @@ def test_abc_512():
     assert abs(mm[1] - 0.703259) < 3e-3 * 0.703259 and abs(mm[0] - 1.486860) < 0.05 * 1.486860
     assert abs(Hreg - r[10]) < 1e-3 * r[10] and abs(H - r[9]) < 0.05 * r[9]
     assert abs(e["mass"] - 0.9796053) < 1e-4 and abs(e["energy"] - 1.0090255) < 5e-3
+
+
+def _paper_run(kind, n, alpha, beta, dt, t_final, every, seed):
+    """One run of the SRP or RVR benchmark at the paper's size: (t, E_kin^i, E_kin^c)
+    every `every` steps, and the maximum relative changes of N and E."""
+    import paper_2003_03590_amd as gp
+    plan = gp.Plan(n, alpha, beta, dt, "c128")
+    plan.autotune(reps=3)
+    if kind == "srp":
+        psi = plan.init_phase(torch.from_numpy(I.srp_spline_theta(n, 32 * math.pi, 4, seed)))
+    else:
+        pairs = [(p["R"], p["d"], p["X"], p["Y"], p["Z"], p["perm"])
+                 for p in I.rvr_draws(800, seed, math.pi / 2, math.pi / 2)]
+        psi = plan.init_rvr(pairs, math.sqrt(alpha / beta))
+    steps = int(round(t_final / dt))
+    e0 = plan.energies(psi)
+    rows = [(0.0, e0["e_kin_i"], e0["e_kin_c"])]
+    dn = de = 0.0
+    done = 0
+    t0 = time.time()
+    while done < steps:
+        k = min(every, steps - done)
+        plan.step_n(psi, k)
+        done += k
+        e = plan.energies(psi)
+        rows.append((done * dt, e["e_kin_i"], e["e_kin_c"]))
+        dn = max(dn, abs(e["mass"] - e0["mass"]) / e0["mass"])
+        de = max(de, abs(e["energy"] - e0["energy"]) / e0["energy"])
+        _log(f"{kind}512: t = {done * dt:.2f}  E_kin^i {e['e_kin_i']:.5f}  E_kin^c {e['e_kin_c']:.5f}"
+             f"  dN {dn:.1e}  dE {de:.1e}  [{time.time() - t0:.0f} s]")
+    plan.close()
+    return np.array(rows), dn, de
+
+
+def test_srp_512():
+    """SRP_c (512^3, alpha = 0.0125, beta = 160, dt = 1/4096, T_f = 6.5, K = 32 pi,
+    N_r = 4), one seed of the paper's ensemble: E_kin^i starts at 0, rises to an
+    early maximum and decays; E_kin^c dominates throughout; N conserved."""
+    r, dn, de = _paper_run("srp", 512, 6.4 / 512, 512 / 3.2, 1.0 / 4096, 6.5, 2048, 0)
+    t, ei, ec = r[:, 0], r[:, 1], r[:, 2]
+    assert ei[0] < 1e-2 * ec[0] and ei.max() > 10 * ei[0]
+    assert t[int(np.argmax(ei))] <= 2.0 and ei[-1] < ei.max()
+    assert np.all(ec > ei)
+    assert dn < 1e-10 and de < 5e-4
+
+
+def test_rvr_512():
+    """RVR_c (512^3, alpha = 0.0125, beta = 160, dt = 1/4096, T_f = 4.5, 800 pairs,
+    R = pi/2, d = pi), one seed: E_kin^i dominates for t < 1, E_kin^c grows after;
+    N conserved."""
+    r, dn, de = _paper_run("rvr", 512, 6.4 / 512, 512 / 3.2, 1.0 / 4096, 4.5, 2048, 0)
+    t, ei, ec = r[:, 0], r[:, 1], r[:, 2]
+    assert np.all(ei[t < 1.0] > ec[t < 1.0]) and ec[t >= 2.0].max() > 2 * ec[0]
+    assert dn < 1e-10 and de < 5e-4
