@@ -361,3 +361,17 @@ def test_argle_on_degenerate_grids(shape):
     assert abs(r["crit_sup"] - cs) < 1e-10 * cs
     assert _rel(phi.cpu().numpy(), ref) < 1e-12
     plan.close()
+
+
+def test_abc_run_conserves_as_printed(abc_a_prepared):
+    """ABC_a: the GP run from the ABC_aIT field (dt = 8e-4, T_f = 10, 12500 steps)
+    against the ABC conservation table: N(0) of the prepared field (1.2e-4 from the
+    printed value; the preparation itself is within 1 %), N conserved to round-off,
+    the maximum energy change of the printed size 5.98e-5 (within a factor 1.5)."""
+    phi, _, _ = abc_a_prepared
+    c = _golden("abc_conservation.txt")["ABC_a"]
+    e0, e, dn, de = _evolve(phi.clone(), int(c[0]), c[1], c[2], c[3], c[4], 250)
+    print(f"ABC_a: N0 {e0['mass']:.7f} E0 {e0['energy']:.7f} E(T) {e['energy']:.7f} dN {dn:.2e} dE {de:.3e}"
+          f" (printed {c[5]} {c[8]} {c[9]} {c[10]})")
+    assert abs(e0["mass"] - c[5]) < 5e-4 and dn < 1e-10
+    assert c[10] / 1.5 < de < 1.5 * c[10]

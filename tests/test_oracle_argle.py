@@ -201,8 +201,9 @@ def test_printed_energies_support_the_pointwise_quantum_reading():
     """E_kin + E_q = 2 alpha^2 sum |k~|^2 |c_k|^2 holds exactly only with E_q taken
     pointwise from psi's derivatives, so E = E_kin^i + E_kin^c + E_q + E_int up to the
     Nyquist entries.  The paper's tables agree: the four energies of TG_aIT, TG_bIT and
-    TG_cIT add up to the E(0) of the runs TG_a, TG_b, TG_c they start (1e-6 relative).
-    (The TG_d row of the conservation table does not match TG_dIT; not used.)"""
+    TG_cIT add up to the E(0) of the runs TG_a, TG_b, TG_c they start (1e-6 relative),
+    and so do those of ABC_aIT..ABC_cIT for ABC_a..ABC_c.  (The TG_d row of the
+    conservation table does not match TG_dIT; not used.)"""
     prep = _rows("tg_argle_energies.txt")
     cons = _rows("tg_conservation.txt")
     for it, run in (("TG_aIT", "TG_a"), ("TG_bIT", "TG_b"), ("TG_cIT", "TG_c")):
@@ -210,6 +211,14 @@ def test_printed_energies_support_the_pointwise_quantum_reading():
         e0 = cons[run][8]
         assert abs(total - e0) < 1e-6 * e0, (it, total, e0)
         assert prep[it][0] == cons[run][0] and prep[it][1] == cons[run][1]
+    # the same holds for all three ABC preparations and their runs
+    aprep = _rows("abc_argle_energies.txt")
+    acons = _rows("abc_conservation.txt")
+    for it, run in (("ABC_aIT", "ABC_a"), ("ABC_bIT", "ABC_b"), ("ABC_cIT", "ABC_c")):
+        total = sum(aprep[it][5:9])
+        e0 = acons[run][8]
+        assert abs(total - e0) < 1e-6 * e0, (it, total, e0)
+        assert aprep[it][0:3] == acons[run][0:3]
     # delta(E) is a maximum over the run, so it is at least the end-point change
     for run, r in cons.items():
         assert r[10] >= abs(r[9] - r[8]) / r[8] - 1e-6, run      # 7 printed digits
