@@ -98,6 +98,31 @@ def run_form(gp, torch, psi0_np, w, prec, steps, warmup, tune=True):
                 energies=energies, spec=spec)
 
 
+def literal_form(torch, plan, psi0_np, step_ms_merged, steps=10):
+    """The literal (un-merged) Strang step of the time-evolution section on the same
+    plan and field: per step two 3-D linear half steps, each a forward 3-D FFT
+    (3 passes), the 3-D multiplier and an inverse 3-D FFT (3 passes), with the
+    nonlinear rotation between them: 30 N^3 S bytes per step against the merged
+    form's 6 N^3 S."""
+    S = 16 if plan.prec == 0 else 8
+    dt = torch.complex128 if S == 16 else torch.complex64
+    psi = torch.from_numpy(psi0_np).to("cuda").to(dt).contiguous()
+    plan.step_literal_n(psi, 1)
+    st = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(st)
+    plan.step_literal_n(psi, steps)
+    b.record(st)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    npts = float(psi0_np.size)
+    per_step = 30.0 * npts * S
+    return {"steps": steps, "ms_per_step": ms, "value": npts / (ms / 1e3), "unit": "grid-point.steps/s",
+            "bytes_per_step": per_step, "hbm_gbs": per_step / (ms / 1e3) / 1e9,
+            "merged_over_literal": ms / step_ms_merged}
+
+
 def ensemble_form(gp, torch, I):
     """The 48-run ensemble (32 at 64^3, 16 at 96^3, complex64, dt = 1e-3, 300 steps)
     advanced by one HIP-graph launch after autotuning; grid-point.steps/s summed
@@ -357,6 +382,7 @@ def main(argv=None):
         "drift_f64": {"dE": f64["dE"], "dN": f64["dN"]},
         "schedule": [f64["plan"].schedule(ax) for ax in range(5)],
     }
+    res["literal_form"] = literal_form(torch, f64["plan"], psi0, sum(f64["step_ms"]) / split_steps)
     if not a.no_fp32:
         f32 = run_form(gp, torch, psi0, w, "c64", a.steps, a.warmup, tune=not a.no_tune)
         v32 = npts * split_steps / f32["wall"]
