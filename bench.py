@@ -31,10 +31,11 @@ WORKLOAD = "tg256"
 DIAG_EVERY = 100
 
 
-def pass_traffic(name="axis_pass_tg256_traffic.json"):
+def pass_traffic(name="axis_pass_tg256_traffic.json", schedules=None):
     """HBM bytes per axis-pass launch from a committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size), or None when
-    the kernel sources changed since the counters were taken."""
+    the kernel sources changed since the counters were taken, or when `schedules`
+    (the x, y, z schedule names of the timed plan) differ from the ones profiled."""
     import hashlib
     path = os.path.join(ROOT, "profiles", name)
     try:
@@ -44,6 +45,11 @@ def pass_traffic(name="axis_pass_tg256_traffic.json"):
             h.update(open(os.path.join(ROOT, f), "rb").read())
         if h.hexdigest() != rec["source_sha256"]:
             return None
+        if schedules is not None:
+            for ax, sched in zip(rec["axes"], schedules):
+                shape = " ".join(sched.split()[:4])          # "N=.. T=.. W=.. R=.."
+                if shape not in ax["kernel"]:
+                    return None
         return rec["traffic_bytes_per_launch"]
     except (OSError, KeyError, ValueError):
         return None
@@ -184,7 +190,8 @@ def large_form(gp, torch, I, steps=5):
            "value": float(n) ** 3 * steps / (ms / 1e3), "unit": "grid-point.steps/s",
            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": gbs / HBM_PEAK_GBS, "per_launch_bytes": per_launch,
-                        "traffic": pass_traffic("axis_pass_rvr1024_traffic.json"),
+                        "traffic": pass_traffic("axis_pass_rvr1024_traffic.json",
+                                                [plan.schedule(ax) for ax in range(3)]),
                         "mean_launch_us": ms * 1e3 / launches},
            "schedule": [plan.schedule(ax) for ax in range(3)]}
     plan.close()
@@ -375,7 +382,8 @@ def main(argv=None):
         "hbm_gbs_per_split_step": 6.0 * npts * S / (sum(f64["step_ms"]) / 1e3 / split_steps) / 1e9,
         "bytes_per_split_step_min": 6.0 * npts * S,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": pass_traffic(),
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": pass_traffic(schedules=[f64["plan"].schedule(ax) for ax in range(3)]),
                      "kernel": "axis_pass (propagator; the nonlinear rotation fused into the carrier axis's pass), "
                                "mean of the three",
                      "per_launch_bytes": bytes_per_pass, "mean_launch_us": f64["mean_pass_ms"] * 1e3},

@@ -284,7 +284,8 @@ GP_API gp_status gp_select_variant(gp_plan_t* p, int32_t axis, int32_t variant);
 /* Autotuner: for every axis of the plan (every size group of a batch plan),
  * time `reps` launches of each compiled schedule variant on `scratch` (dev, one
  * state of the plan's largest run; its contents are overwritten) with HIP
- * events, and keep the fastest; then the xy choice (axis 3), timed with as many
+ * events, and keep the fastest (timings within 1 % count as ties, resolved to the
+ * lower variant index, so repeated tunings agree); then the xy choice (axis 3), timed with as many
  * runs per launch as the size group holds; then, for single plans with separate
  * passes, the nonlinear carrier (axis 4), timed as whole linear steps.  cache_path
  * (may be NULL): a JSON file of

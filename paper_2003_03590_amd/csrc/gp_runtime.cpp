@@ -1498,6 +1498,10 @@ static gp_status time_calls(gp_plan_s* p, int reps, double* us, const std::funct
 // `runs` copies of the scratch state at once (the ensemble launches a size group
 // together, which changes how well each option fills the GPU; the copies all
 // alias `scratch`, whose contents are undefined afterwards)
+// Timings within 1 % count as ties, resolved to the candidate tried first (the lower
+// variant index, the first axis, separate passes), so that repeated tunings agree.
+constexpr double TUNE_TIE = 0.99;
+
 static gp_status tune_xy(gp_plan_s* p, void* scratch, int reps, int runs, int* choice) {
   gp_status st;
   *choice = 0;
@@ -1531,7 +1535,7 @@ static gp_status tune_xy(gp_plan_s* p, void* scratch, int reps, int runs, int* c
          p->plane.e->fn[0](g, (unsigned)p->d.n[2], (unsigned)runs, p->stream);
        })) != GP_OK)
     return st;
-  *choice = t_plane < t_sep ? 1 : 0;
+  *choice = t_plane < TUNE_TIE * t_sep ? 1 : 0;
   return GP_OK;
 }
 
@@ -1554,7 +1558,7 @@ static gp_status tune_nl(gp_plan_s* p, void* scratch, int reps, int* choice) {
          })) != GP_OK)
       return st;
     if (inner != GP_OK) return inner;
-    if (us < best) { best = us; *choice = a; }
+    if (us < TUNE_TIE * best) { best = us; *choice = a; }
   }
   return GP_OK;
 }
@@ -1580,7 +1584,7 @@ static gp_status tune_plan(gp_plan_s* p, void* scratch, int reps, std::map<std::
       if ((st = gp_select_variant(p, a, v)) != GP_OK) return st;
       double us = 0;
       if ((st = time_axis(p, a, scratch, reps, &us)) != GP_OK) return st;
-      if (us < best) { best = us; bestv = v; }
+      if (us < TUNE_TIE * best) { best = us; bestv = v; }
     }
     if ((st = gp_select_variant(p, a, bestv)) != GP_OK) return st;
     cache[key] = bestv;
