@@ -200,18 +200,19 @@ def large_form(gp, torch, I, steps=5):
     return out
 
 
-ARGLE_BYTES_PER_POINT = 33.5    # x S bytes per grid point and ARGLE step (see argle_form)
+ARGLE_BYTES_PER_POINT = 30.5    # x S bytes per grid point and ARGLE step (see argle_form)
 
 
 def argle_form(gp, torch, I, steps=200, warmup=20):
     """Imaginary-time (ARGLE) preparation at 256^3 complex128 in the configuration
     of the grid-convergence run TG_h (alpha = 0.05, beta = 40, dtau = 6.25e-3, Taylor-
     Green ansatz and flow): `steps` steps timed with HIP events on the plan's stream.
-    Algorithmic bytes per step, in units of S = 16 bytes per point: three derivative
-    passes (read phi, write d_j: 6), the explicit part (read phi, d_x, d_y, d_z and the
-    three real velocity planes, write n: 6.5), forward 3-D transforms of phi and n
-    (3 passes each, 12), the diagonal solve (read both, write phi: 3) and the inverse
-    3-D transform (6): 33.5 S."""
+    Algorithmic bytes per step, in units of S = 16 bytes per point: the x and y
+    derivative passes (read phi, write d_j: 4), the z-derivative pass that forms the
+    explicit part in place of d_z (read phi, d_x, d_y and the three real velocity
+    planes, write n: 5.5), forward 3-D transforms of phi and n (3 passes each, 12),
+    the diagonal solve (read both, write phi: 3) and the inverse 3-D transform (6):
+    30.5 S."""
     import numpy as np
     n, alpha, beta, dtau = 256, 0.05, 40.0, 6.25e-3
     plan = gp.Plan(n, alpha, beta, 1e-3, "c128")

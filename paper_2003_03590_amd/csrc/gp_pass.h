@@ -45,8 +45,10 @@ __device__ __forceinline__ GPK_GLOBAL X* gptr_mut(void* p) { return (GPK_GLOBAL 
 enum PassKind { CONTIG = 0, STRIDED = 1 };
 enum PassMode { PROP = 0, FWD = 1, INV = 2 };
 // pointwise work fused in front of the transform (PRO_KIN: none, but accumulate
-// sum k_j^2 |F_j v|^2 after the forward transform for the kinetic energy)
-enum Prologue { PRO_NONE = 0, PRO_NL = 1, PRO_ADJ_NL = 2, PRO_DENSITY = 3, PRO_KIN = 4 };
+// sum k_j^2 |F_j v|^2 after the forward transform for the kinetic energy;
+// PRO_ARGLE: none, but turn the derivative after the inverse transform into the
+// explicit part of the imaginary-time step)
+enum Prologue { PRO_NONE = 0, PRO_NL = 1, PRO_ADJ_NL = 2, PRO_DENSITY = 3, PRO_KIN = 4, PRO_ARGLE = 5 };
 
 // per-run pointers of a grouped (ensemble) launch: run = blockIdx.y
 struct RunPtrs {
@@ -63,7 +65,11 @@ struct PassArgs {
   void* out;               // output field (may equal in)
   const void* mult;        // PROP: multiplier in lane order (N_j FP64 complex entries)
   const void* tw;          // per-stage twiddles W_{R M}^{lo k} (Tab<Real> entries, layout above)
-  const void* aux;         // PRO_ADJ_NL: forward state phi at the same points
+  const void* aux;         // PRO_ADJ_NL, PRO_ARGLE: the state phi at the same points
+  const void* aux2;        // PRO_ARGLE: d phi / dx and d phi / dy at the same points
+  const void* aux3;
+  const void* vel;         // PRO_ARGLE: velocity planes v_x, v_y, v_z (Real, one field each)
+  double q4a;              // PRO_ARGLE: 1 / (4 alpha)
   const double* ksq;       // k_j^2 in position order (kinetic accumulation)
   double* kin_partial;     // per-workgroup partial sum of k_j^2 |F_j v|^2 (or null)
   double nl_coef;          // beta * dt of the nonlinear prologue
@@ -383,6 +389,23 @@ __global__ __launch_bounds__(S::THREADS) void axis_pass(PassArgs a) {
           for (int j = 0; j < B; ++j)
             v[j + B * r] = pmul(v[j + B * r], tab_at(mult, r * (S::N / S::rad(L)) + t + T * j));
         inverse_all<Real, S, KIND, L>(v, lds, t, col, tw);
+        if constexpr (PRO == PRO_ARGLE) {
+          // v holds d phi / dz (this pass is the z derivative); replace it by the explicit
+          // part of the imaginary-time step at the same points:
+          //   n = -i v.grad phi + (beta - |v|^2/(4 alpha) - beta |phi|^2) phi
+          const long ntot = a.npencils * (long)S::N;
+          const auto vel = gptr<Real>(a.vel);
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            const long idx = cur.bbase + (long)((e * estep + cur.loff) / (long)sizeof(C));
+            const C f = gptr<C>(a.aux)[idx], gx = gptr<C>(a.aux2)[idx], gy = gptr<C>(a.aux3)[idx];
+            const double ux = vel[idx], uy = vel[ntot + idx], uz = vel[2 * ntot + idx];
+            const double gr = ux * gx.x + uy * gy.x + uz * v[e].x, gi = ux * gx.y + uy * gy.y + uz * v[e].y;
+            const double pr = f.x, pi = f.y;
+            const double c = a.nl_coef - (ux * ux + uy * uy + uz * uz) * a.q4a - a.nl_coef * (pr * pr + pi * pi);
+            v[e] = mk(Real(gi + c * pr), Real(-gr + c * pi));
+          }
+        }
       } else {  // FWD: reorder to natural frequency order
         if constexpr (S::NS > 1) exchange<Real, S, KIND, L, -1>(lds, v, t, col);
         const Real sc = Real(a.scale);
@@ -425,6 +448,6 @@ void launch_pass(const PassArgs& a, unsigned grid, unsigned runs, hipStream_t st
 }
 
 // kernel variants compiled for every schedule
-enum Variant { V_PROP = 0, V_PROP_NL, V_PROP_ADJ, V_PROP_KIN, V_FWD, V_FWD_DENSITY, V_INV, V_COUNT };
+enum Variant { V_PROP = 0, V_PROP_NL, V_PROP_ADJ, V_PROP_KIN, V_FWD, V_FWD_DENSITY, V_INV, V_PROP_ARGLE, V_COUNT };
 
 }  // namespace gpk

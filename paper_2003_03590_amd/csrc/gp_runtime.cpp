@@ -1024,20 +1024,43 @@ gp_status gp_helicity(gp_plan_t* p, const void* psi, void* work, double* out, do
   return GP_OK;
 }
 
-// nsteps steps of the semi-implicit backward Euler scheme; work slots 0..2.  The
-// explicit part n overwrites d/dz in place (its only reader), which streams faster
-// than writing a separate field.
+// the z-derivative pass with the explicit part of the imaginary-time step fused after
+// its inverse transform: out = n(phi, d/dx phi, d/dy phi, d/dz phi, v)
+static gp_status argle_z_pass(gp_plan_s* p, const void* phi, const void* d0, const void* d1, const void* v,
+                              void* out) {
+  Axis& A = p->ax[2];
+  PassArgs g{};
+  g.in = phi; g.out = out; g.mult = A.deriv; g.tw = A.tw; g.aux = phi; g.aux2 = d0; g.aux3 = d1; g.vel = v;
+  g.ksq = A.ksq; g.nl_coef = p->d.beta; g.q4a = 1.0 / (4.0 * p->d.alpha); g.scale = 1.0;
+  g.npencils = A.npencils; g.inner = A.inner; g.outer = A.outer; g.es = A.es;
+  A.e->fn[A.kind][V_PROP_ARGLE](g, A.blocks, 1, p->stream);
+  return check_launch(p);
+}
+
+// nsteps steps of the semi-implicit backward Euler scheme; work slots 0..2.  With a
+// z axis the explicit part n comes out of the z-derivative pass (d/dz never reaches
+// memory); otherwise a pointwise kernel forms it and overwrites d/dz in place.
 static gp_status argle_steps(gp_plan_s* p, void* phi, const void* v, double dtau, int64_t nsteps, void* work) {
   gp_status st;
   void* d0 = field(p, work, 0);
   void* d1 = field(p, work, 1);
   void* d2 = field(p, work, 2);
   void* q = d2;
+  const bool fused = p->ax[2].n > 1;
   const double a = 0.5 * dtau * p->d.alpha, inv_n = 1.0 / (double)p->ntot;
   for (int64_t s = 0; s < nsteps; ++s) {
-    if ((st = derivatives(p, phi, work, false)) != GP_OK) return st;
-    launch_argle_explicit(p->prec, phi, d0, d1, d2, v, q, p->ntot, p->d.alpha, p->d.beta, p->stream);
-    if ((st = check_launch(p)) != GP_OK) return st;
+    if (fused) {
+      for (int ax = 0; ax < 2; ++ax) {
+        void* out = field(p, work, ax);
+        if (p->ax[ax].n == 1) HIPCHK(p, hipMemsetAsync(out, 0, p->ntot * p->S, p->stream));
+        else if ((st = pass(p, ax, V_PROP, phi, out, p->ax[ax].deriv)) != GP_OK) return st;
+      }
+      if ((st = argle_z_pass(p, phi, d0, d1, v, q)) != GP_OK) return st;
+    } else {
+      if ((st = derivatives(p, phi, work, false)) != GP_OK) return st;
+      launch_argle_explicit(p->prec, phi, d0, d1, d2, v, q, p->ntot, p->d.alpha, p->d.beta, p->stream);
+      if ((st = check_launch(p)) != GP_OK) return st;
+    }
     if ((st = fwd3_unnorm(p, phi)) != GP_OK) return st;
     if ((st = fwd3_unnorm(p, q)) != GP_OK) return st;
     launch_argle_solve(p->prec, phi, q, p->d.n[0], p->d.n[1], p->d.n[2], a, dtau, inv_n, p->stream);
