@@ -240,11 +240,15 @@ def rvr_draws(n_pairs: int, seed: int, rmin: float = 0.3, rmax: float = 0.8):
     return out
 
 
-def rvr_psi(n: int, xi: float, n_pairs: int, seed: int, rmin=0.3, rmax=0.8) -> np.ndarray:
-    """Product of n_pairs random vortex-ring pairs on an n^3 grid (complex128)."""
+def rvr_psi(n: int, xi: float, n_pairs: int, seed: int, rmin=0.3, rmax=0.8,
+            zslab=None) -> np.ndarray:
+    """Product of n_pairs random vortex-ring pairs on an n^3 grid (complex128).
+    ``zslab = (lo, hi)`` evaluates only the planes lo <= z < hi (every point is
+    computed on its own, so slabs put together equal the whole field)."""
     g = grid(n)
-    coords = (g[None, None, :], g[None, :, None], g[:, None, None])   # x, y, z
-    psi = np.ones((n, n, n), dtype=np.complex128)
+    lo, hi = (0, n) if zslab is None else zslab
+    coords = (g[None, None, :], g[None, :, None], g[lo:hi, None, None])   # x, y, z
+    psi = np.ones((hi - lo, n, n), dtype=np.complex128)
     for p in rvr_draws(n_pairs, seed, rmin, rmax):
         a = [coords[i] for i in PERMUTATIONS[p["perm"]]]
         sx = np.mod(a[0] - p["X"], TWO_PI)
@@ -287,8 +291,10 @@ def alpha_beta_table1(n: int):
 
 _XI2 = 2.0 * (TWO_PI / 256)
 _XI3 = 3.0 * (TWO_PI / 1024)
+_XI3S = 3.0 * (TWO_PI / 256)
 _A2, _B2 = alpha_beta_from_xi(_XI2)
 _A3, _B3 = alpha_beta_from_xi(_XI3)
+_A3S, _B3S = alpha_beta_from_xi(_XI3S)
 
 WORKLOADS = {
     "srp32": dict(n=32, prec=("c128",), alpha=1.0, beta=1.0, dt=1e-3, steps=200,
@@ -298,6 +304,10 @@ WORKLOADS = {
                   diag_every=100),
     "rvr1024": dict(n=1024, prec=("c64",), alpha=_A3, beta=_B3, dt=2.5e-4, steps=500,
                     ic=("rvr", dict(xi=_XI3, n_pairs=40, seed=1)), diag_every=50),
+    # the 1024^3 random-vortex-ring construction at 256^3: the same 40 pairs (seed 1),
+    # core width three grid spacings, alpha beta = 2, the same dt and final time
+    "rvr256": dict(n=256, prec=("c128", "c64"), alpha=_A3S, beta=_B3S, dt=2.5e-4, steps=500,
+                   ic=("rvr", dict(xi=_XI3S, n_pairs=40, seed=1)), diag_every=50),
     "adj128": dict(n=128, prec=("c128",), alpha=0.05, beta=40.0, dt=1e-3, steps=400,
                    ic=("srp", dict(K=6, seed=2)), ckpt=20, smin=4, smax=12,
                    fd_h=1e-6, fd_dirs=16, fd_seed0=1000),

@@ -24,6 +24,11 @@
  *     values, in which case it synchronizes that stream before returning.
  *   - Every call returns gp_status; nothing throws, exits or prints.  After a
  *     HIP error the plan is unusable (later calls return GP_ERR_STATE).
+ *   - Calls that work on one grid return GP_ERR_STATE for a batch plan.
+ *   - Testing the error paths: with the environment variable GP_FAULT_INJECT
+ *     set to "alloc", every device allocation fails with GP_ERR_NOMEM before
+ *     hipMalloc is called; set to "launch", every kernel-launch check reports
+ *     a HIP error (GP_ERR_HIP, plan unusable) although the kernel runs normally.
  *   - A plan is not thread-safe; distinct plans are.
  *   - Supported axis lengths: 1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96,
  *     128, 192, 256, 384, 512, 768, 1024 (GP_ERR_UNSUPPORTED otherwise).

@@ -21,7 +21,11 @@ Two independent 1-D engines are provided:
   prime) Cooley-Tukey FFT, vectorised over the other axes.
 
 ``fft3``/``ifft3`` pick the dense DFT for N <= 64 and the FFT above, or the
-engine named by ``engine=``.
+engine named by ``engine=``.  ``engine`` may also be a callable
+``engine(a, axis, sign)`` that returns the unnormalised 1-D transform along
+``axis``; it exists so that a driver can split the independent pencils of one
+transform over several processes (each process still calling ``transform_axis``
+with the default rule), which leaves every value unchanged.
 """
 from __future__ import annotations
 
@@ -109,6 +113,8 @@ def fft_axis(a: np.ndarray, axis: int, sign: int = -1) -> np.ndarray:
 
 
 def transform_axis(a: np.ndarray, axis: int, sign: int, engine: str | None = None) -> np.ndarray:
+    if callable(engine):
+        return engine(a, axis, sign)
     n = np.shape(a)[axis]
     if engine is None:
         engine = "dft" if n <= NAIVE_MAX else "fft"

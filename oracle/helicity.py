@@ -17,7 +17,10 @@ Readings: v_par divides by |grad psi|^2, which vanishes at the critical points
 of psi (not at vortex cores, where |grad psi|^2 ~ 1/(2 xi^2)); there v_reg is
 set to 0 where |grad psi|^2 <= 1e-12 <|grad psi|^2> (a symmetric field such as
 the Taylor-Green state has such points exactly on the grid, and the quantum
-vorticity vanishes there).  All derivatives are spectral with the first-derivative wavenumbers
+vorticity vanishes there).  The floor is not a free parameter: the values of
+|grad psi|^2 it removes are rounding-level zeros (below 1e-24 of the mean), and
+H_reg is unchanged to 1e-12 as the floor moves from 1e-20 to 1e-10
+(tests/test_oracle_helicity.py).  All derivatives are spectral with the first-derivative wavenumbers
 (Nyquist entry 0), second derivatives are two first derivatives (-k_i k_j);
 v = 2 alpha Im(psi* grad psi)/|psi|^2 (0 where psi = 0); omega = curl v taken
 spectrally from that v.  Spectra: integer shells round(|k|), H(k) = sum over the

@@ -234,6 +234,27 @@ __device__ __forceinline__ void sincos_rot(float a, float* sn, float* cs) {
   }
 }
 
+// exp(i a) - 1 = cm1 + i sn for FP32 data, with cm1 = cos a - 1 to full relative
+// precision (the series gives it directly; larger angles use -2 sin^2(a/2)).
+// The rotation is then applied as v + v (cm1 + i sn): the factor's norm is 1 to
+// O(u a), where fl(cos a) + i fl(sin a) is off by up to u -- for |a| below
+// ~2.4e-4, fl(cos a) = 1 while sin a != 0 -- a gain that repeats at a point
+// every step with the slowly varying angle and so adds up coherently.
+__device__ __forceinline__ void sincos_m1(float a, float* sn, float* cm1) {
+  if (fabsf(a) <= 0.0625f) {
+    const float r2 = a * a;
+    const float ps = fmaf(float(ct::inv_fact(5)), r2, float(-ct::inv_fact(3)));
+    *sn = fmaf(ps * r2, a, a);
+    const float pc = fmaf(float(ct::inv_fact(4)), r2, -0.5f);
+    *cm1 = pc * r2;
+  } else {
+    float sh, ch;
+    sincos_rot(0.5f * a, &sh, &ch);
+    *sn = 2.0f * sh * ch;
+    *cm1 = -2.0f * sh * sh;
+  }
+}
+
 constexpr int smallest_factor(int n) {
   if (n % 4 == 0) return 4;                        // radix-4 first: trivial internal rotations
   if (n % 2 == 0) return 2;
@@ -271,8 +292,20 @@ struct Dft<3, SGN, Real> {
     cplx<Real> m = mk(a.x - h * t.x, a.y - h * t.y);
     x[0] = a + t;
     // X1 = a + b w + c w^2,  w = exp(SGN 2pi i/3) = -1/2 + i s
-    x[1] = mk(m.x - s * d.y, m.y + s * d.x);
-    x[2] = mk(m.x + s * d.y, m.y - s * d.x);
+    Real sdx, sdy;
+    if constexpr (sizeof(Real) == 4) {
+      // s carried as hi + lo: an FP32-rounded s makes |w| != 1 by ~3e-8, a gain
+      // on every mode not divisible by 3 that repeats in each radix-3 stage
+      constexpr double sd = SGN * 0.86602540378443864676372317075293618;
+      constexpr float shi = float(sd), slo = float(sd - double(shi));
+      sdx = fmaf(shi, d.x, slo * d.x);
+      sdy = fmaf(shi, d.y, slo * d.y);
+    } else {
+      sdx = s * d.x;
+      sdy = s * d.y;
+    }
+    x[1] = mk(m.x - sdy, m.y + sdx);
+    x[2] = mk(m.x + sdy, m.y - sdx);
   }
 };
 

@@ -255,12 +255,20 @@ __device__ __forceinline__ void inverse_all(cplx<Real>* v, cplx<Real>* lds, int 
 }
 
 // nonlinear sub-step S(dt, N): v <- v exp(-i beta (|v|^2 - 1) dt), in the working precision
-// (an FP64 factor for FP32 data was measured to change neither mass nor energy drift)
 template <class Real>
 __device__ __forceinline__ cplx<Real> nl_rotate(cplx<Real> v, double coef) {
   Real s, c;
   sincos_rot(-Real(coef) * (cabs2(v) - Real(1)), &s, &c);
   return cmul(v, mk(c, s));
+}
+// FP32: v + v (cos a - 1 + i sin a), see sincos_m1; the small correction is formed
+// first, so the result carries one rounding at the size of v
+template <>
+__device__ __forceinline__ cplx<float> nl_rotate<float>(cplx<float> v, double coef) {
+  float s, cm1;
+  sincos_m1(-float(coef) * (cabs2(v) - 1.0f), &s, &cm1);
+  const float dx = fmaf(v.x, cm1, -v.y * s), dy = fmaf(v.y, cm1, v.x * s);
+  return mk(v.x + dx, v.y + dy);
 }
 
 // adjoint of the linearised nonlinear sub-step at phi:

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <map>
@@ -203,8 +204,18 @@ namespace {
     }                                                                                        \
   } while (0)
 
+// Host-side fault switch for testing the error paths: GP_FAULT_INJECT=alloc makes
+// every device allocation of the library fail (GP_ERR_NOMEM) before hipMalloc is
+// called; GP_FAULT_INJECT=launch makes every kernel-launch check report a HIP error
+// (the kernel itself was launched and runs normally).  Unset, it costs one getenv.
+bool fault_injected(const char* what) {
+  const char* e = getenv("GP_FAULT_INJECT");
+  return e && strcmp(e, what) == 0;
+}
+
 gp_status check_launch(gp_plan_s* p) {
   hipError_t e = hipGetLastError();
+  if (e == hipSuccess && fault_injected("launch")) e = hipErrorLaunchFailure;
   if (e != hipSuccess) {
     p->broken = true;
     return fail(GP_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
@@ -215,6 +226,7 @@ gp_status check_launch(gp_plan_s* p) {
 gp_status dev_alloc(gp_plan_s* p, void** ptr, size_t bytes) {
   *ptr = nullptr;
   if (bytes == 0) bytes = 16;
+  if (fault_injected("alloc")) return fail(GP_ERR_NOMEM, "hipMalloc(%zu) failed: injected fault", bytes);
   hipError_t e = hipMalloc(ptr, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -442,6 +454,14 @@ gp_status validate_desc(const gp_desc* d) {
 gp_status usable(const gp_plan_s* p) {
   if (!p) return fail(GP_ERR_ARG, "null plan");
   if (p->broken) return fail(GP_ERR_STATE, "plan is unusable after an earlier HIP error");
+  return GP_OK;
+}
+
+// entry points that work on one grid: a batch plan has no tables of its own
+gp_status usable_single(const gp_plan_s* p) {
+  gp_status st = usable(p);
+  if (st != GP_OK) return st;
+  if (p->is_batch) return fail(GP_ERR_STATE, "batch plan: this call takes a single-grid plan");
   return GP_OK;
 }
 
@@ -730,7 +750,7 @@ gp_status gp_select_variant(gp_plan_t* p, int32_t axis, int32_t variant) {
 }
 
 gp_status gp_init_phase(gp_plan_t* p, const double* theta, void* psi) {
-  gp_status st = usable(p);
+  gp_status st = usable_single(p);
   if (st != GP_OK) return st;
   if (!theta || !psi) return fail(GP_ERR_ARG, "null theta or psi");
   launch_init_phase(p->prec, theta, psi, p->ntot, p->stream);
@@ -738,7 +758,7 @@ gp_status gp_init_phase(gp_plan_t* p, const double* theta, void* psi) {
 }
 
 gp_status gp_init_rvr(gp_plan_t* p, const double* pairs, int32_t npairs, double xi, void* psi) {
-  gp_status st = usable(p);
+  gp_status st = usable_single(p);
   if (st != GP_OK) return st;
   if (!pairs || !psi || npairs < 0) return fail(GP_ERR_ARG, "null argument or negative pair count");
   if (!(xi > 0.0) || !std::isfinite(xi)) return fail(GP_ERR_ARG, "core width xi must be positive");
@@ -768,7 +788,7 @@ gp_status gp_init_rvr(gp_plan_t* p, const double* pairs, int32_t npairs, double 
 }
 
 gp_status gp_substep_linear(gp_plan_t* p, void* psi, int32_t axis, double s) {
-  gp_status st = usable(p);
+  gp_status st = usable_single(p);
   if (st != GP_OK) return st;
   if (!psi) return fail(GP_ERR_ARG, "null psi");
   if (axis < 0 || axis > 2) return fail(GP_ERR_ARG, "axis %d", axis);
@@ -792,7 +812,7 @@ gp_status gp_substep_linear(gp_plan_t* p, void* psi, int32_t axis, double s) {
 }
 
 gp_status gp_substep_nonlinear(gp_plan_t* p, void* psi, double s) {
-  gp_status st = usable(p);
+  gp_status st = usable_single(p);
   if (st != GP_OK) return st;
   if (!psi) return fail(GP_ERR_ARG, "null psi");
   if (!std::isfinite(s)) return fail(GP_ERR_ARG, "non-finite s");
@@ -801,7 +821,7 @@ gp_status gp_substep_nonlinear(gp_plan_t* p, void* psi, double s) {
 }
 
 gp_status gp_step_n(gp_plan_t* p, void* psi, int64_t nsteps) {
-  gp_status st = usable(p);
+  gp_status st = usable_single(p);
   if (st != GP_OK) return st;
   if (p->is_batch) return fail(GP_ERR_STATE, "batch plan: use gp_step_n_batch");
   if (!psi) return fail(GP_ERR_ARG, "null psi");
@@ -809,7 +829,7 @@ gp_status gp_step_n(gp_plan_t* p, void* psi, int64_t nsteps) {
 }
 
 gp_status gp_step_literal_n(gp_plan_t* p, void* psi, int64_t nsteps) {
-  gp_status st = usable(p);
+  gp_status st = usable_single(p);
   if (st != GP_OK) return st;
   if (!psi) return fail(GP_ERR_ARG, "null psi");
   const bool back = nsteps < 0;
@@ -833,7 +853,7 @@ gp_status gp_step_literal_n(gp_plan_t* p, void* psi, int64_t nsteps) {
 }
 
 gp_status gp_fft3(gp_plan_t* p, const void* in, void* out, int32_t dir) {
-  gp_status st = usable(p);
+  gp_status st = usable_single(p);
   if (st != GP_OK) return st;
   if (!in || !out) return fail(GP_ERR_ARG, "null field");
   if (dir != -1 && dir != 1) return fail(GP_ERR_ARG, "dir must be -1 or +1");
@@ -841,7 +861,7 @@ gp_status gp_fft3(gp_plan_t* p, const void* in, void* out, int32_t dir) {
 }
 
 gp_status gp_energies(gp_plan_t* p, const void* psi, void* work, gp_energy* out) {
-  gp_status st = usable(p);
+  gp_status st = usable_single(p);
   if (st != GP_OK) return st;
   if (!psi || !work || !out) return fail(GP_ERR_ARG, "null argument");
   if ((st = diagnose(p, psi, work)) != GP_OK) return st;
@@ -849,7 +869,7 @@ gp_status gp_energies(gp_plan_t* p, const void* psi, void* work, gp_energy* out)
 }
 
 gp_status gp_spectra(gp_plan_t* p, const void* psi, void* work, double* out, int32_t nshell, gp_energy* energies) {
-  gp_status st = usable(p);
+  gp_status st = usable_single(p);
   if (st != GP_OK) return st;
   if (!psi || !work || !out) return fail(GP_ERR_ARG, "null argument");
   if (nshell != p->nshell) return fail(GP_ERR_ARG, "nshell %d != %d", nshell, p->nshell);
@@ -862,7 +882,7 @@ gp_status gp_spectra(gp_plan_t* p, const void* psi, void* work, double* out, int
 }
 
 gp_status gp_structure_fn(gp_plan_t* p, const void* psi, void* work, int32_t p_order, double* out) {
-  gp_status st = usable(p);
+  gp_status st = usable_single(p);
   if (st != GP_OK) return st;
   if (!psi || !work || !out) return fail(GP_ERR_ARG, "null argument");
   if (p_order != 2) return fail(GP_ERR_UNSUPPORTED, "structure function order %d (only 2)", p_order);
@@ -890,7 +910,7 @@ gp_status gp_structure_fn(gp_plan_t* p, const void* psi, void* work, int32_t p_o
 
 gp_status gp_structure_fn_velocity(gp_plan_t* p, const void* psi, void* work, int32_t p_order, double* out,
                                    double* mean_v2) {
-  gp_status st = usable(p);
+  gp_status st = usable_single(p);
   if (st != GP_OK) return st;
   if (p->is_batch) return fail(GP_ERR_STATE, "batch plan: diagnostics run on single plans");
   if (!psi || !work || !out) return fail(GP_ERR_ARG, "null argument");
@@ -927,7 +947,7 @@ gp_status gp_structure_fn_velocity(gp_plan_t* p, const void* psi, void* work, in
 }
 
 gp_status gp_mach(gp_plan_t* p, const void* psi, void* work, double* out) {
-  gp_status st = usable(p);
+  gp_status st = usable_single(p);
   if (st != GP_OK) return st;
   if (p->is_batch) return fail(GP_ERR_STATE, "batch plan: diagnostics run on single plans");
   if (!psi || !work || !out) return fail(GP_ERR_ARG, "null argument");
@@ -963,7 +983,7 @@ size_t gp_helicity_work_bytes(const gp_plan_t* p) {
 }
 
 gp_status gp_helicity(gp_plan_t* p, const void* psi, void* work, double* out, double* spec, int32_t nshell) {
-  gp_status st = usable(p);
+  gp_status st = usable_single(p);
   if (st != GP_OK) return st;
   if (p->is_batch) return fail(GP_ERR_STATE, "batch plan: diagnostics run on single plans");
   if (!psi || !work || !out) return fail(GP_ERR_ARG, "null argument");
@@ -1150,7 +1170,7 @@ gp_status gp_argle_run(gp_plan_t* p, void* phi, const void* v, double dtau, int6
 
 gp_status gp_loss_ekin_i_shells(gp_plan_t* p, const void* psi, void* work, int32_t smin, int32_t smax, double* J,
                                 void* lam) {
-  gp_status st = usable(p);
+  gp_status st = usable_single(p);
   if (st != GP_OK) return st;
   if (!psi || !work || !J || !lam) return fail(GP_ERR_ARG, "null argument");
   if (smin < 0 || smax < smin) return fail(GP_ERR_ARG, "bad shell range %d..%d", smin, smax);
@@ -1192,7 +1212,7 @@ gp_status gp_loss_ekin_i_shells(gp_plan_t* p, const void* psi, void* work, int32
 }
 
 gp_status gp_adjoint_step_n(gp_plan_t* p, const void* psi_seg_start, void* lam, int64_t nsteps, void* tape) {
-  gp_status st = usable(p);
+  gp_status st = usable_single(p);
   if (st != GP_OK) return st;
   if (!psi_seg_start || !lam || !tape) return fail(GP_ERR_ARG, "null argument");
   if (nsteps < 0) return fail(GP_ERR_ARG, "nsteps must be >= 0");
@@ -1250,7 +1270,7 @@ gp_status gp_adjoint_step_n(gp_plan_t* p, const void* psi_seg_start, void* lam, 
 }
 
 gp_status gp_phase_grad(gp_plan_t* p, const void* psi0, const void* lam0, double* dJ_dtheta) {
-  gp_status st = usable(p);
+  gp_status st = usable_single(p);
   if (st != GP_OK) return st;
   if (!psi0 || !lam0 || !dJ_dtheta) return fail(GP_ERR_ARG, "null argument");
   launch_phase_grad(p->prec, psi0, lam0, dJ_dtheta, p->ntot, p->stream);

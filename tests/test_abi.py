@@ -91,3 +91,19 @@ def test_new_entry_points_reject_null_plans_without_gpu():
         assert lib.gp_last_error().decode()
     assert lib.gp_helicity_work_bytes(None) == 0
     assert lib.gp_schedule_name(None, 4) == b""
+
+
+@needs_lib
+def test_allocation_fault_is_nomem_without_gpu(monkeypatch):
+    """GP_FAULT_INJECT=alloc: plan creation stops at its first device allocation
+    (before any HIP call) with GP_ERR_NOMEM and a message, and hands back no plan."""
+    import paper_2003_03590_amd as gp
+    from paper_2003_03590_amd import _lib
+    lib = gp.lib()
+    monkeypatch.setenv("GP_FAULT_INJECT", "alloc")
+    h = C.c_void_p()
+    for prec in (0, 1):
+        d = _lib.gp_desc((C.c_int32 * 3)(16, 12, 8), 1.0, 1.0, 1e-3, prec, 0)
+        assert lib.gp_plan(C.byref(d), None, C.byref(h)) == _lib.GP_ERR_NOMEM
+        assert h.value is None
+        assert "injected" in lib.gp_last_error().decode()

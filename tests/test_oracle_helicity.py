@@ -91,3 +91,33 @@ def test_taylor_green_ansatz_has_no_helicity():
         r = Hh.helicity(I.tg_psi(n, xi, e), 0.3)
         assert abs(r["H"]) < 1e-12 and abs(r["H_reg"]) < 1e-12
         assert np.abs(r["spec"]).max() < 1e-10
+
+
+def test_regularization_floor_is_not_a_free_parameter(monkeypatch):
+    """The floor that zeroes v_reg where |grad psi|^2 <= floor <|grad psi|^2> only
+    removes the 0/0 of v_par at exact critical points of psi.  On random, ABC,
+    straight-vortex-line and Taylor-Green fields, H_reg is unchanged to 1e-12
+    relative as the floor moves over ten decades (1e-20 ... 1e-10): below 1e-10 the
+    only points any field has are rounding-level zeros of |grad psi|^2 (the
+    Taylor-Green state's critical points on the grid), and none lie in between."""
+    n = 16
+    z, y, x = _grid3(n)
+    fields = {
+        "random": (I.random_field(n, seed=11), 0.3),
+        "abc": (I.abc_psi(n, 0.05), 0.05),
+        "lines": ((np.sin(x) + 1j * np.sin(y)) * np.exp(2j * z) * np.ones((n, n, n)), 0.3),
+        "tg": (I.tg_psi(n, 0.25, 1), 0.2),
+    }
+    for name, (psi, alpha) in fields.items():
+        g2 = sum(np.abs(d) ** 2 for d in gp.gradient(psi))
+        ratio = g2 / g2.mean()
+        # nothing between rounding level and 1e-8 of the mean
+        assert not np.any((ratio > 1e-24) & (ratio <= 1e-8)), name
+        vals = []
+        for floor in (1e-20, 1e-14, 1e-12, 1e-10):
+            monkeypatch.setattr(Hh, "G2_FLOOR", floor)
+            vals.append(Hh.helicity(psi, alpha)["H_reg"])
+        scale = max(abs(v) for v in vals) or 1.0
+        assert max(vals) - min(vals) <= 1e-12 * scale, (name, vals)
+        if name == "tg":
+            assert np.any(ratio <= 1e-24)          # the field that needs the floor has such points
