@@ -149,6 +149,19 @@ GP_API gp_status gp_fft3(gp_plan_t* p, const void* in, void* out, int32_t dir);
  * Synchronizes.  GP_ERR_NONFINITE if any value is NaN/Inf. */
 GP_API gp_status gp_energies(gp_plan_t* p, const void* psi, void* work, gp_energy* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture
+ * set up beforehand, tight serving loops, harnesses that forbid hipMalloc):
+ * gp_energies with its diagnostics workspace in a static device array of
+ * GP_STATIC_WORK_BYTES (64 MiB) that the library holds on every GPU it runs on
+ * until the process ends, so the caller passes no workspace and nothing is
+ * allocated or freed.  The plan (created earlier by gp_plan) must need at most
+ * that much: 4 * N^3 * S bytes, i.e. up to 96^3 complex128 or 128^3 complex64;
+ * larger grids return GP_ERR_ARG before any GPU work.  Results equal those of
+ * gp_energies.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (from several threads or streams) race.  Synchronizes. */
+#define GP_STATIC_WORK_BYTES (64u << 20)
+GP_API gp_status gp_energies_static(gp_plan_t* p, const void* psi, gp_energy* out);
+
 /* Shell spectra (spectra section, Parseval per unit volume): out is host
  * [4][nshell] doubles, rows E_kin^i(s), E_kin^c(s), E_q(s), E_int(s), each summing
  * to its energy.  energies (host, may be NULL) receives gp_energy of the same

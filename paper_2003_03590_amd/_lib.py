@@ -58,6 +58,7 @@ SIGNATURES = {
     "gp_step_literal_n": (ST, [P, P, C.c_int64]),
     "gp_fft3": (ST, [P, P, P, C.c_int32]),
     "gp_energies": (ST, [P, P, P, C.POINTER(gp_energy)]),
+    "gp_energies_static": (ST, [P, P, C.POINTER(gp_energy)]),
     "gp_spectra": (ST, [P, P, P, C.POINTER(C.c_double), C.c_int32, C.POINTER(gp_energy)]),
     "gp_structure_fn": (ST, [P, P, P, C.c_int32, C.POINTER(C.c_double)]),
     "gp_loss_ekin_i_shells": (ST, [P, P, P, C.c_int32, C.c_int32, C.POINTER(C.c_double), P]),

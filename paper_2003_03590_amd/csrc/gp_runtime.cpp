@@ -626,6 +626,31 @@ gp_status copy_energies(gp_plan_s* p, gp_energy* out) {
 }
 
 }  // namespace
+
+// Used by the entry point that allocates nothing (gp_noalloc.hip): argument checks
+// of gp_energies for a workspace of at most max_bytes, the energies on a given
+// workspace, and the error message of a failure found there.
+size_t energies_work_bytes(const gp_plan_s* p) { return 4 * (size_t)p->ntot * p->S; }
+
+gp_status energies_static_args(gp_plan_s* p, const void* psi, const gp_energy* out, size_t max_bytes) {
+  gp_status st = usable_single(p);
+  if (st != GP_OK) return st;
+  if (!psi || !out) return fail(GP_ERR_ARG, "null argument");
+  const size_t need = energies_work_bytes(p);
+  if (need > max_bytes)
+    return fail(GP_ERR_ARG, "grid needs %zu bytes of diagnostics workspace; the static workspace holds %zu", need,
+                max_bytes);
+  return GP_OK;
+}
+
+gp_status energies_on(gp_plan_s* p, const void* psi, void* work, gp_energy* out) {
+  gp_status st = diagnose(p, psi, work);
+  if (st != GP_OK) return st;
+  return copy_energies(p, out);
+}
+
+gp_status report_error(gp_status st, const char* msg) { return fail(st, "%s", msg); }
+
 }  // namespace gpk
 
 // =================================================================== C ABI
