@@ -82,9 +82,13 @@ def run_form(gp, torch, psi0_np, w, prec, steps, warmup, tune=True):
     # restart from the initial condition so the timed run is the workload itself
     psi.copy_(torch.from_numpy(psi0_np).to("cuda").to(dt))
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    per_run = w["steps"] // DIAG_EVERY          # bench steps of one whole workload
+    dev0 = torch.from_numpy(psi0_np).to("cuda").to(dt)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
+        if i and i % per_run == 0:               # the workload again from its initial condition
+            psi.copy_(dev0)
         ev[i][0].record(stream)
         plan.step_n(psi, DIAG_EVERY)
         ev[i][1].record(stream)
@@ -100,6 +104,7 @@ def run_form(gp, torch, psi0_np, w, prec, steps, warmup, tune=True):
     dE = max(abs(e["energy"] - E0) for e in energies) / E0
     dN = max(abs(e["mass"] - N0) for e in energies) / N0
     out = psi.to(torch.complex128).cpu().numpy()
+    del dev0
     return dict(plan=plan, wall=wall, step_ms=step_ms, mean_pass_ms=mean_pass_ms, dE=dE, dN=dN, psi=out,
                 energies=energies, spec=spec)
 
@@ -153,12 +158,19 @@ def ensemble_form(gp, torch, I):
     el = time.perf_counter() - t
     e1 = bp.energies(states)
     pts = sum(float(r["n"]) ** 3 for r in runs)
+    # algorithmic bytes: a run on the xy-plane pass reads and writes its state twice per
+    # step (plane pass + z pass), otherwise three times (x, y, z passes); the call's
+    # opening half step adds one more step's worth
+    plane = [bp.schedule(i, 3).startswith("xy: plane") for i in range(len(runs))]
+    nbytes = sum((4.0 if pl else 6.0) * float(r["n"]) ** 3 * 8 for r, pl in zip(runs, plane)) * (w["steps"] + 1)
     return {"value": pts * w["steps"] / el, "unit": "grid-point.steps/s (summed over runs)",
             "runs": len(runs), "steps": w["steps"], "seconds": el,
-            "hbm_GBs": 6.0 * pts * 8 * (w["steps"] + 1) / el / 1e9,
+            "hbm_GBs": nbytes / el / 1e9, "bytes": nbytes,
+            "plane_pass_runs": int(sum(plane)),
             "max_dN": float(np.max(np.abs(e1[:, 0] - e0[:, 0]) / e0[:, 0])),
             "max_dE": float(np.max(np.abs(e1[:, 1] - e0[:, 1]) / e0[:, 1])),
-            "launch": "one HIP graph (grouped launches per size and axis)"}
+            "launch": "one HIP graph of grouped pass launches (one launch per size group and pass, "
+                      "the runs of a group on the second grid dimension)"}
 
 
 def large_form(gp, torch, I, steps=5):
@@ -185,6 +197,28 @@ def large_form(gp, torch, I, steps=5):
     launches = 3 * (steps + 1)
     per_launch = 2.0 * float(n) ** 3 * 8
     gbs = per_launch * launches / (ms / 1e3) / 1e9
+    # each axis pass alone (the propagator sub-step), and a device copy of the same
+    # bytes (read 8 GiB, write 8 GiB): what this machine's HBM delivers to a plain stream
+    axis = {}
+    for ax in range(3):
+        plan.substep_linear(psi, ax, w["dt"])
+        torch.cuda.synchronize()
+        a.record(st)
+        for _ in range(3):
+            plan.substep_linear(psi, ax, w["dt"])
+        b.record(st)
+        torch.cuda.synchronize()
+        axis["xyz"[ax]] = per_launch / (a.elapsed_time(b) / 3 / 1e3) / 1e9
+    x = torch.empty_like(psi)
+    x.copy_(psi)
+    torch.cuda.synchronize()
+    a.record(st)
+    for _ in range(3):
+        x.copy_(psi)
+    b.record(st)
+    torch.cuda.synchronize()
+    copy_gbs = per_launch / (a.elapsed_time(b) / 3 / 1e3) / 1e9
+    del x
     out = {"workload": "rvr1024: 1024^3 complex64, 40 random vortex-ring pairs (seed 1), dt = 2.5e-4",
            "steps": steps, "ms_per_step": ms / steps,
            "value": float(n) ** 3 * steps / (ms / 1e3), "unit": "grid-point.steps/s",
@@ -192,7 +226,12 @@ def large_form(gp, torch, I, steps=5):
                         "frac": gbs / HBM_PEAK_GBS, "per_launch_bytes": per_launch,
                         "traffic": pass_traffic("axis_pass_rvr1024_traffic.json",
                                                 [plan.schedule(ax) for ax in range(3)]),
-                        "mean_launch_us": ms * 1e3 / launches},
+                        "traffic_source": "profiles/axis_pass_rvr1024_traffic.json (null once the kernel "
+                                          "sources or schedules differ from the profiled ones)",
+                        "mean_launch_us": ms * 1e3 / launches,
+                        "copy_gbs": copy_gbs, "frac_of_copy": gbs / copy_gbs,
+                        "axis_gbs": axis, "axis_frac": {k: v / HBM_PEAK_GBS for k, v in axis.items()},
+                        "axis_frac_of_copy": {k: v / copy_gbs for k, v in axis.items()}},
            "schedule": [plan.schedule(ax) for ax in range(3)]}
     plan.close()
     del psi
@@ -378,12 +417,16 @@ def main(argv=None):
         "config": {"workload": "tg256: 256^3 Taylor-Green ansatz psi_4^2, xi=2*(2pi/256), alpha=0.069420, "
                                "beta=28.810, dt=5e-4, 1000 steps, energy split + shell spectra every 100 steps",
                    "grid": [n, n, n], "prec": "complex128", "split_steps_timed": split_steps,
-                   "bench_step": "100 Strang steps + gp_spectra"},
+                   "workload_runs_timed": split_steps / w["steps"],
+                   "bench_step": "100 Strang steps + gp_spectra; every 10 bench steps the workload "
+                                 "restarts from its initial condition"},
         "value_step_only": step_only,
         "hbm_gbs_per_split_step": 6.0 * npts * S / (sum(f64["step_ms"]) / 1e3 / split_steps) / 1e9,
         "bytes_per_split_step_min": 6.0 * npts * S,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
+                     "cache_resident": "the 256 MiB state fits the 256 MB last-level cache; the HBM-bound "
+                                       "form is large_1024_c64.roofline",
                      "traffic": pass_traffic(schedules=[f64["plan"].schedule(ax) for ax in range(3)]),
                      "kernel": "axis_pass (propagator; the nonlinear rotation fused into the carrier axis's pass), "
                                "mean of the three",

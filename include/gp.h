@@ -280,7 +280,8 @@ GP_API const char* gp_last_error(void);
 
 /* Name of the compiled FFT schedule used for an axis, e.g. "N=256 T=16 W=8 R=16x16".
  * axis 3 names the xy choice: "xy: separate passes" or "xy: plane N=.. T=..";
- * axis 4 the pass that carries the nonlinear rotation ("nl: x pass", ...). */
+ * axis 4 the pass that carries the nonlinear rotation ("nl: x pass", ...).  For a
+ * batch plan the index is 5 * run + axis (the names of that run's schedules). */
 GP_API const char* gp_schedule_name(const gp_plan_t* p, int32_t axis);
 
 /* Number of compiled schedule variants for an axis length and precision, and

@@ -273,7 +273,9 @@ class Plan:
 
 
 class BatchPlan:
-    """Ensemble of independent runs (sizes may differ) advanced by one graph launch."""
+    """Ensemble of independent runs (sizes may differ) advanced by one HIP graph
+    launch: one grouped pass launch per size group and pass (runs of one size share
+    it, run = second grid dimension), recorded once per step count."""
 
     def __init__(self, runs, prec="c64", device=None, stream=None):
         torch = _torch()
@@ -317,6 +319,11 @@ class BatchPlan:
     def step_n(self, states, nsteps: int):
         _check(lib().gp_step_n_batch(self._h, self._ptrs(states), int(nsteps)))
         return states
+
+    def schedule(self, run: int, axis: int) -> str:
+        """Schedule name of one run's axis (0-2), its xy choice (3) or its nonlinear
+        carrier (4)."""
+        return lib().gp_schedule_name(self._h, 5 * int(run) + int(axis)).decode()
 
     def select_xy(self, variant: int):
         """0: separate x and y passes; 1: one xy-plane pass for every run with a plane

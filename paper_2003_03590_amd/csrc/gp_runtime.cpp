@@ -706,7 +706,12 @@ int32_t gp_nshell(const gp_plan_t* p) { return p ? p->nshell : 0; }
 const char* gp_last_error(void) { return g_err.c_str(); }
 
 const char* gp_schedule_name(const gp_plan_t* p, int32_t axis) {
-  if (!p || axis < 0 || axis > 4) return "";
+  if (!p || axis < 0) return "";
+  if (p->is_batch) {         // run-major: index 5 * run + axis
+    const size_t r = (size_t)axis / 5;
+    return r < p->runs.size() ? p->runs[r]->sched_name[axis % 5].c_str() : "";
+  }
+  if (axis > 4) return "";
   return p->sched_name[axis].c_str();
 }
 
@@ -1319,8 +1324,12 @@ gp_status gp_plan_batch(const gp_desc* runs, int32_t nruns, void* hip_stream, gp
   p->d = runs[0];
   p->stream = (hipStream_t)hip_stream;
   bool own_stream = false;
-  if (!p->stream) {            // graph capture needs a non-legacy stream
-    hipError_t e = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking);
+  if (!p->stream) {
+    // graph capture needs a stream other than the legacy null stream; a blocking
+    // stream keeps the null stream's order (work on either waits for the other), so
+    // states written by the caller on the null stream before gp_step_n_batch, and
+    // read on it afterwards, are ordered with the graph without any event
+    hipError_t e = hipStreamCreateWithFlags(&p->stream, hipStreamDefault);
     if (e != hipSuccess) { delete p; return fail(GP_ERR_HIP, "hipStreamCreate: %s", hipGetErrorString(e)); }
     own_stream = true;
   }
@@ -1374,6 +1383,8 @@ static gp_status batch_record(gp_plan_s* p, void* const* psis, int64_t nsteps) {
             e.mult2 = r->plane.my[t == 0 ? th : tf];
           }
         }
+    // a launch of the previous graph may still read the table: let it finish
+    HIPCHK(p, hipStreamSynchronize(p->stream));
     if (g.nptrs < h.size()) {
       if (g.d_ptrs) (void)hipFree(g.d_ptrs);
       g.d_ptrs = nullptr;
