@@ -241,14 +241,17 @@ def rvr_draws(n_pairs: int, seed: int, rmin: float = 0.3, rmax: float = 0.8):
 
 
 def rvr_psi(n: int, xi: float, n_pairs: int, seed: int, rmin=0.3, rmax=0.8,
-            zslab=None) -> np.ndarray:
+            zslab=None, yslab=None, xslab=None) -> np.ndarray:
     """Product of n_pairs random vortex-ring pairs on an n^3 grid (complex128).
-    ``zslab = (lo, hi)`` evaluates only the planes lo <= z < hi (every point is
-    computed on its own, so slabs put together equal the whole field)."""
+    ``zslab = (lo, hi)`` (likewise ``yslab``, ``xslab``) evaluates only the points
+    with lo <= z < hi; every point is computed on its own, so blocks put together
+    equal the whole field."""
     g = grid(n)
-    lo, hi = (0, n) if zslab is None else zslab
-    coords = (g[None, None, :], g[None, :, None], g[lo:hi, None, None])   # x, y, z
-    psi = np.ones((hi - lo, n, n), dtype=np.complex128)
+    zl, zh = (0, n) if zslab is None else zslab
+    yl, yh = (0, n) if yslab is None else yslab
+    xl, xh = (0, n) if xslab is None else xslab
+    coords = (g[None, None, xl:xh], g[None, yl:yh, None], g[zl:zh, None, None])   # x, y, z
+    psi = np.ones((zh - zl, yh - yl, xh - xl), dtype=np.complex128)
     for p in rvr_draws(n_pairs, seed, rmin, rmax):
         a = [coords[i] for i in PERMUTATIONS[p["perm"]]]
         sx = np.mod(a[0] - p["X"], TWO_PI)

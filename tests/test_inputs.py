@@ -98,3 +98,13 @@ def test_srp_spline_rejects_bad_sizes_and_is_seeded():
     a = I.srp_spline_theta(16, 1.0, 4, 5)
     assert np.array_equal(a, I.srp_spline_theta(16, 1.0, 4, 5))
     assert not np.array_equal(a, I.srp_spline_theta(16, 1.0, 4, 6))
+
+
+def test_rvr_blocks_equal_the_whole_field():
+    """Sub-blocks of the ring-pair field (used to sample the paper-size generator)
+    are the corresponding parts of the whole field, bit for bit."""
+    a = I.rvr_psi(16, 0.2, 3, 1)
+    b = I.rvr_psi(16, 0.2, 3, 1, zslab=(3, 7), yslab=(2, 9), xslab=(5, 16))
+    assert np.array_equal(a[3:7, 2:9, 5:16], b)
+    c = np.concatenate([I.rvr_psi(16, 0.2, 3, 1, zslab=(0, 5)), I.rvr_psi(16, 0.2, 3, 1, zslab=(5, 16))])
+    assert np.array_equal(a, c)
