@@ -219,6 +219,23 @@ def large_form(gp, torch, I, steps=5):
     torch.cuda.synchronize()
     copy_gbs = per_launch / (a.elapsed_time(b) / 3 / 1e3) / 1e9
     del x
+    # both forms of the linear steps, whichever the autotuner kept (fixed layout in
+    # place, or layout-rotating passes through one more state)
+    chosen = plan.schedule(5)
+    forms = {}
+    for v, name in ((0, "fixed"), (1, "rotating")):
+        plan.select_variant(5, v)
+        plan.step_n(psi, 2)
+        torch.cuda.synchronize()
+        a.record(st)
+        plan.step_n(psi, steps)
+        b.record(st)
+        torch.cuda.synchronize()
+        fms = a.elapsed_time(b)
+        forms[name] = {"ms_per_step": fms / steps,
+                       "axis_pass_gbs": per_launch * launches / (fms / 1e3) / 1e9,
+                       "frac": per_launch * launches / (fms / 1e3) / 1e9 / HBM_PEAK_GBS}
+    plan.select_variant(5, 1 if chosen.startswith("layout: rotating") else 0)
     out = {"workload": "rvr1024: 1024^3 complex64, 40 random vortex-ring pairs (seed 1), dt = 2.5e-4",
            "steps": steps, "ms_per_step": ms / steps,
            "value": float(n) ** 3 * steps / (ms / 1e3), "unit": "grid-point.steps/s",
@@ -232,7 +249,8 @@ def large_form(gp, torch, I, steps=5):
                         "copy_gbs": copy_gbs, "frac_of_copy": gbs / copy_gbs,
                         "axis_gbs": axis, "axis_frac": {k: v / HBM_PEAK_GBS for k, v in axis.items()},
                         "axis_frac_of_copy": {k: v / copy_gbs for k, v in axis.items()}},
-           "schedule": [plan.schedule(ax) for ax in range(3)]}
+           "layout_forms": forms,
+           "schedule": [plan.schedule(ax) for ax in range(6)]}
     plan.close()
     del psi
     torch.cuda.empty_cache()
@@ -432,7 +450,7 @@ def main(argv=None):
                                "mean of the three",
                      "per_launch_bytes": bytes_per_pass, "mean_launch_us": f64["mean_pass_ms"] * 1e3},
         "drift_f64": {"dE": f64["dE"], "dN": f64["dN"]},
-        "schedule": [f64["plan"].schedule(ax) for ax in range(5)],
+        "schedule": [f64["plan"].schedule(ax) for ax in range(6)],
     }
     res["literal_form"] = literal_form(torch, f64["plan"], psi0, sum(f64["step_ms"]) / split_steps)
     if not a.no_fp32:
@@ -445,7 +463,7 @@ def main(argv=None):
                        "dE": f32["dE"], "dN": f32["dN"], "rel_l2_psi_vs_f64_gpu": rel,
                        "axis_pass_gbs": ach32, "axis_pass_frac": ach32 / HBM_PEAK_GBS,
                        "mean_launch_us": f32["mean_pass_ms"] * 1e3,
-                       "schedule": [f32["plan"].schedule(ax) for ax in range(5)]}
+                       "schedule": [f32["plan"].schedule(ax) for ax in range(6)]}
     if not a.no_ensemble:
         res["ensemble"] = ensemble_form(gp, torch, I)
     if not a.no_large:

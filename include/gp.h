@@ -280,8 +280,9 @@ GP_API const char* gp_last_error(void);
 
 /* Name of the compiled FFT schedule used for an axis, e.g. "N=256 T=16 W=8 R=16x16".
  * axis 3 names the xy choice: "xy: separate passes" or "xy: plane N=.. T=..";
- * axis 4 the pass that carries the nonlinear rotation ("nl: x pass", ...).  For a
- * batch plan the index is 5 * run + axis (the names of that run's schedules). */
+ * axis 4 the pass that carries the nonlinear rotation ("nl: x pass", ...); axis 5
+ * the form of the linear steps ("layout: fixed" or "layout: rotating ...").  For a
+ * batch plan the index is 6 * run + axis (the names of that run's schedules). */
 GP_API const char* gp_schedule_name(const gp_plan_t* p, int32_t axis);
 
 /* Number of compiled schedule variants for an axis length and precision, and
@@ -295,8 +296,15 @@ GP_API const char* gp_schedule_name(const gp_plan_t* p, int32_t axis);
  * GP_ERR_UNSUPPORTED.  axis 4 (single plans, separate passes) selects the axis pass
  * that carries the nonlinear rotation as its prologue and runs first in each
  * linear step (variant 0, 1, 2 = x, y, z; the linear sub-steps commute, so any
- * order is the same split step); default: the first axis of length > 1.  Batch
- * plans: GP_ERR_STATE for every axis but 3. */
+ * order is the same split step); default: the first axis of length > 1.  axis 5
+ * (single cubic plans) selects the form of the linear steps of gp_step_n: variant
+ * 0 (default) the fixed layout, every pass in place; variant v >= 1 the v-th
+ * compiled rotating schedule: layout-rotating passes along x, z, y, each reading whole contiguous pencils and writing the state
+ * in a turned layout ([z][y][x] -> [y][x][z] -> [x][z][y] -> [z][y][x]), out of
+ * place between psi and one more state that the plan allocates on selection (N^3 S
+ * bytes, released again by variant 0); psi holds the [z][y][x] state whenever
+ * gp_step_n returns.  GP_ERR_UNSUPPORTED for other shapes or lengths without a
+ * rotating schedule.  Batch plans: GP_ERR_STATE for every axis but 3. */
 GP_API int32_t gp_variant_count(int32_t n, int32_t prec);
 GP_API gp_status gp_select_variant(gp_plan_t* p, int32_t axis, int32_t variant);
 
@@ -306,7 +314,9 @@ GP_API gp_status gp_select_variant(gp_plan_t* p, int32_t axis, int32_t variant);
  * events, and keep the fastest (timings within 1 % count as ties, resolved to the
  * lower variant index, so repeated tunings agree); then the xy choice (axis 3), timed with as many
  * runs per launch as the size group holds; then, for single plans with separate
- * passes, the nonlinear carrier (axis 4), timed as whole linear steps.  cache_path
+ * passes, the nonlinear carrier (axis 4), timed as whole linear steps, and for
+ * cubic grids with a rotating schedule the layout form (axis 5), timed as whole
+ * linear steps (the rotating form's workspace is released when it loses).  cache_path
  * (may be NULL): a JSON file of
  * earlier choices keyed by GPU architecture, precision, grid shape and axis;
  * cached choices are applied without timing and new ones are added.

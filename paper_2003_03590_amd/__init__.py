@@ -117,7 +117,7 @@ class Plan:
         scratch = _torch().zeros(self.shape, dtype=self.dtype, device=self.device)
         _check(lib().gp_autotune(self._h, C.c_void_p(_ptr(scratch)), int(reps),
                                  cache.encode() if cache else None))
-        return [self.schedule(a) for a in range(5)]
+        return [self.schedule(a) for a in range(6)]
 
     # ---------------------------------------------------------------- method
     def init_phase(self, theta, out=None):
@@ -321,9 +321,9 @@ class BatchPlan:
         return states
 
     def schedule(self, run: int, axis: int) -> str:
-        """Schedule name of one run's axis (0-2), its xy choice (3) or its nonlinear
-        carrier (4)."""
-        return lib().gp_schedule_name(self._h, 5 * int(run) + int(axis)).decode()
+        """Schedule name of one run's axis (0-2), its xy choice (3), its nonlinear
+        carrier (4) or its layout form (5)."""
+        return lib().gp_schedule_name(self._h, 6 * int(run) + int(axis)).decode()
 
     def select_xy(self, variant: int):
         """0: separate x and y passes; 1: one xy-plane pass for every run with a plane

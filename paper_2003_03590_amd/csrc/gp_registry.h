@@ -6,6 +6,7 @@
 
 #include "gp_pass.h"
 #include "gp_plane.h"
+#include "gp_rot.h"
 
 namespace gpk {
 
@@ -74,6 +75,32 @@ PassEntry make_entry(int prec, int variant) {
   return e;
 }
 
+// layout-rotating passes (cubic grids; one schedule serves all three axes)
+struct RotEntry {
+  int n, prec;
+  PassEntry sched;         // schedule descriptor (table layout; no launchers)
+  RotLauncher fn[2];       // [0] propagator, [1] with the nonlinear prologue
+};
+
+std::vector<RotEntry>& rot_registry();
+
+struct RotRegistrar {
+  explicit RotRegistrar(const RotEntry& e) { rot_registry().push_back(e); }
+};
+
+template <class Real, class S>
+RotEntry make_rot_entry(int prec) {
+  static_assert(S::THREADS % 64 == 0, "workgroup must be whole wavefronts");
+  RotEntry e{};
+  e.n = S::N; e.prec = prec;
+  e.sched.n = S::N; e.sched.prec = prec; e.sched.variant = -1;
+  e.sched.T = S::T; e.sched.W = S::W; e.sched.NS = S::NS; e.sched.threads = S::THREADS;
+  for (int s = 0; s < 3; ++s) e.sched.radix[s] = s < S::NS ? S::rad(s) : 1;
+  e.fn[0] = &launch_rot<Real, S, PRO_NONE>;
+  e.fn[1] = &launch_rot<Real, S, PRO_NL>;
+  return e;
+}
+
 }  // namespace gpk
 
 #define GPK_CAT2(a, b) a##b
@@ -86,3 +113,7 @@ PassEntry make_entry(int prec, int variant) {
 #define GPK_PLANE(REAL, PREC, N, T, R0, R1, R2)                                                  \
   static ::gpk::PlaneRegistrar GPK_CAT(gpk_plane_, __LINE__)(                                    \
       ::gpk::make_plane_entry<REAL, ::gpk::Sched<N, T, N, R0, R1, R2>>(PREC));
+// GPK_ROT(real, prec, N, T, W, R0, R1, R2): layout-rotating pass schedule
+#define GPK_ROT(REAL, PREC, N, T, W, R0, R1, R2)                                                  \
+  static ::gpk::RotRegistrar GPK_CAT(gpk_rot_, __LINE__)(                                         \
+      ::gpk::make_rot_entry<REAL, ::gpk::Sched<N, T, W, R0, R1, R2>>(PREC));

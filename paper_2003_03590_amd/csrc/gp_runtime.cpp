@@ -30,6 +30,11 @@ std::vector<PlaneEntry>& plane_registry() {
   return r;
 }
 
+std::vector<RotEntry>& rot_registry() {
+  static std::vector<RotEntry> r;
+  return r;
+}
+
 namespace {
 
 thread_local std::string g_err;
@@ -169,7 +174,8 @@ struct gp_plan_s {
   double* h_result = nullptr;      // pinned mirror
   bool broken = false;
   bool own_stream = false;         // stream created by the plan (batch plans on the null stream)
-  std::string sched_name[5];       // x, y, z axis schedules; [3]: the xy-plane choice; [4]: the nonlinear carrier
+  std::string sched_name[6];       // x, y, z axis schedules; [3]: the xy-plane choice; [4]: the nonlinear
+                                   // carrier; [5]: fixed-layout or layout-rotating linear steps
   int nl_axis = -1;                // axis pass that carries the nonlinear prologue (-1: first real axis)
   // xy-plane pass (x and y sub-steps fused; needs nx == ny with a compiled plane schedule)
   struct Plane {
@@ -179,6 +185,15 @@ struct gp_plan_s {
     void* mx[NTAU] = {};
     void* my[NTAU] = {};
   } plane;
+  // layout-rotating passes (cubic grids): every linear step as x, z, y passes that
+  // turn the layout, out of place between psi and one state of workspace
+  struct Rot {
+    const RotEntry* e = nullptr;
+    bool on = false;
+    void* work = nullptr;          // N^3 S bytes, allocated when first selected
+    void* tw = nullptr;
+    void* mult[NTAU] = {};
+  } rot;
   RunPtrs* d_tune_ptrs = nullptr;  // autotuner: grouped timing launches
   size_t n_tune_ptrs = 0;
   // ensemble
@@ -398,6 +413,7 @@ gp_status plan_init(gp_plan_s* p, const gp_desc* d, hipStream_t stream) {
   p->plane.e = (d->n[0] == d->n[1] && d->n[0] > 1) ? find_plane(d->n[0], p->prec) : nullptr;
   p->sched_name[3] = "xy: separate passes";
   p->sched_name[4] = "nl: first axis";
+  p->sched_name[5] = "layout: fixed";
   // reduction partials
   const long kin_n = (long)p->ax[0].blocks + p->ax[1].blocks + p->ax[2].blocks;
   if ((st = dev_alloc(p, (void**)&p->kin_part, std::max(1L, kin_n) * sizeof(double))) != GP_OK) return st;
@@ -434,6 +450,7 @@ void plan_free(gp_plan_s* p) {
   for (void* a : p->allocs) (void)hipFree(a);
   for (auto& g : p->groups) if (g.d_ptrs) (void)hipFree(g.d_ptrs);
   if (p->h_result) (void)hipHostFree(p->h_result);
+  if (p->rot.work) (void)hipFree(p->rot.work);
   if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
   delete p;
 }
@@ -521,6 +538,29 @@ gp_status linear_all(gp_plan_s* p, void* psi, int tau, bool with_nl, double nl) 
   return GP_OK;
 }
 
+// L(tau) as three layout-rotating passes x, z, y from `in` ([z][y][x]) through the
+// workspace to `out` ([z][y][x]): in -> [y][x][z] -> [x][z][y] -> [z][y][x].  The
+// passes alternate between the two states, so in = out only after an even number
+// of such steps; `in` and `out` are psi and the workspace in turn.
+gp_status rot_linear(gp_plan_s* p, void* a, void* b, int tau, bool with_nl, double nl) {
+  const RotEntry& e = *p->rot.e;
+  const unsigned grid = (unsigned)((long)e.n * e.n / e.sched.W);
+  RotArgs g{};
+  g.mult = p->rot.mult[tau];
+  g.tw = p->rot.tw;
+  g.nl_coef = nl;
+  gp_status st;
+  g.in = a; g.out = b;                     // x pass (nonlinear prologue)
+  e.fn[with_nl ? 1 : 0](g, grid, p->stream);
+  if ((st = check_launch(p)) != GP_OK) return st;
+  g.in = b; g.out = a;                     // z pass
+  e.fn[0](g, grid, p->stream);
+  if ((st = check_launch(p)) != GP_OK) return st;
+  g.in = a; g.out = b;                     // y pass
+  e.fn[0](g, grid, p->stream);
+  return check_launch(p);
+}
+
 gp_status step_n(gp_plan_s* p, void* psi, int64_t nsteps) {
   if (nsteps == 0) return GP_OK;
   const bool back = nsteps < 0;
@@ -528,9 +568,66 @@ gp_status step_n(gp_plan_s* p, void* psi, int64_t nsteps) {
   const int th = back ? TAU_MH : TAU_H, tf = back ? TAU_MDT : TAU_DT;
   const double nl = p->d.beta * (back ? -p->d.dt : p->d.dt);
   gp_status st;
+  if (p->rot.on) {
+    // n + 1 linear steps; each rotating one moves the state to the other buffer, so
+    // with an odd count the opening half step runs in place with the fixed-layout
+    // passes and the state ends in psi
+    int64_t first = 0;
+    if ((n + 1) % 2 == 1) {
+      if ((st = linear_all(p, psi, th, false, 0.0)) != GP_OK) return st;
+      first = 1;
+    }
+    void* cur = psi;
+    void* oth = p->rot.work;
+    for (int64_t k = first; k <= n; ++k) {
+      const int tau = (k == 0 || k == n) ? th : tf;
+      if ((st = rot_linear(p, cur, oth, tau, k > 0, nl)) != GP_OK) return st;
+      std::swap(cur, oth);
+    }
+    return GP_OK;
+  }
   if ((st = linear_all(p, psi, th, false, 0.0)) != GP_OK) return st;
   for (int64_t s = 0; s < n; ++s)
     if ((st = linear_all(p, psi, s + 1 < n ? tf : th, true, nl)) != GP_OK) return st;
+  return GP_OK;
+}
+
+// the v-th compiled rotating schedule of length n (registration order)
+const RotEntry* find_rot(int n, int prec, int v = 0) {
+  for (const auto& e : rot_registry())
+    if (e.n == n && e.prec == prec && v-- == 0) return &e;
+  return nullptr;
+}
+
+// tables of the rotating passes (the same for the three axes of a cube) and the
+// workspace state
+gp_status build_rot(gp_plan_s* p) {
+  auto& R = p->rot;
+  gp_status st;
+  if (fault_injected("alloc")) return fail(GP_ERR_NOMEM, "rotating-pass workspace: injected fault");
+  if (!R.tw && (st = upload_cplx(p, &R.tw, stage_twiddles(R.e->sched))) != GP_OK) return st;
+  const double alpha = p->d.alpha, dt = p->d.dt;
+  const double taus[NTAU] = {0.5 * dt, dt, -0.5 * dt, -dt};
+  const int n = R.e->n;
+  for (int t = 0; t < NTAU; ++t) {
+    std::vector<double> m(2 * n);
+    for (int k = 0; k < n; ++k) {
+      const double kk = (double)kfreq(k, n);
+      const double ph = alpha * kk * kk * taus[t];
+      const int i = tab_idx(R.e->sched, k);
+      m[2 * i] = std::cos(ph) / n;
+      m[2 * i + 1] = -std::sin(ph) / n;
+    }
+    if (!R.mult[t] && (st = upload_c128(p, &R.mult[t], m)) != GP_OK) return st;
+  }
+  if (R.work) return GP_OK;
+  hipError_t e = hipMalloc(&R.work, (size_t)p->ntot * p->S);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    R.work = nullptr;
+    return fail(GP_ERR_NOMEM, "hipMalloc(%zu) of the rotating-pass workspace failed: %s", (size_t)p->ntot * p->S,
+                hipGetErrorString(e));
+  }
   return GP_OK;
 }
 
@@ -707,11 +804,11 @@ const char* gp_last_error(void) { return g_err.c_str(); }
 
 const char* gp_schedule_name(const gp_plan_t* p, int32_t axis) {
   if (!p || axis < 0) return "";
-  if (p->is_batch) {         // run-major: index 5 * run + axis
-    const size_t r = (size_t)axis / 5;
-    return r < p->runs.size() ? p->runs[r]->sched_name[axis % 5].c_str() : "";
+  if (p->is_batch) {         // run-major: index 6 * run + axis
+    const size_t r = (size_t)axis / 6;
+    return r < p->runs.size() ? p->runs[r]->sched_name[axis % 6].c_str() : "";
   }
-  if (axis > 4) return "";
+  if (axis > 5) return "";
   return p->sched_name[axis].c_str();
 }
 
@@ -751,6 +848,40 @@ gp_status gp_select_variant(gp_plan_t* p, int32_t axis, int32_t variant) {
     snprintf(nm, sizeof nm, "xy: plane N=%d T=%d R=%dx%dx%d", p->plane.e->n, p->plane.e->T, p->plane.e->radix[0],
              p->plane.e->radix[1], p->plane.e->radix[2]);
     p->sched_name[3] = nm;
+    return GP_OK;
+  }
+  if (axis == 5) {   // linear steps: 0 = fixed layout, in place; 1 = layout-rotating passes
+    if (variant == 0) {
+      if (p->rot.work) {
+        HIPCHK(p, p->stream ? hipStreamSynchronize(p->stream) : hipDeviceSynchronize());
+        (void)hipFree(p->rot.work);
+        p->rot.work = nullptr;
+      }
+      p->rot.on = false;
+      p->sched_name[5] = "layout: fixed";
+      return GP_OK;
+    }
+    if (variant < 1) return fail(GP_ERR_ARG, "layout variant %d (0 = fixed, 1.. = rotating schedules)", variant);
+    const int n = p->d.n[0];
+    const bool cube = p->d.n[1] == n && p->d.n[2] == n;
+    if (!cube || !find_rot(n, p->prec))
+      return fail(GP_ERR_UNSUPPORTED, "no layout-rotating schedule for %dx%dx%d (cubes of a compiled length only)",
+                  p->d.n[0], p->d.n[1], p->d.n[2]);
+    const RotEntry* e = find_rot(n, p->prec, variant - 1);
+    if (!e) return fail(GP_ERR_ARG, "no rotating schedule %d for n = %d", variant - 1, n);
+    HIPCHK(p, p->stream ? hipStreamSynchronize(p->stream) : hipDeviceSynchronize());
+    if (p->rot.e && (p->rot.e->sched.NS != e->sched.NS || p->rot.e->sched.radix[0] != e->sched.radix[0] ||
+                     p->rot.e->sched.radix[1] != e->sched.radix[1] || p->rot.e->sched.radix[2] != e->sched.radix[2])) {
+      p->rot.tw = nullptr;           // another radix order: other tables (the old ones are freed with the plan)
+      for (auto& m : p->rot.mult) m = nullptr;
+    }
+    p->rot.e = e;
+    if ((st = build_rot(p)) != GP_OK) return st;
+    p->rot.on = true;
+    char nm[128];
+    snprintf(nm, sizeof nm, "layout: rotating N=%d T=%d W=%d R=%dx%dx%d", e->n, e->sched.T, e->sched.W,
+             e->sched.radix[0], e->sched.radix[1], e->sched.radix[2]);
+    p->sched_name[5] = nm;
     return GP_OK;
   }
   if (axis == 4) {   // which axis pass carries the nonlinear prologue: 0, 1, 2 = x, y, z
@@ -1642,6 +1773,46 @@ static gp_status tune_nl(gp_plan_s* p, void* scratch, int reps, int* choice) {
   return GP_OK;
 }
 
+// linear steps: fixed-layout passes (in place) against layout-rotating passes (out of
+// place through one more state); the rotating form is kept only if it wins by 1 %,
+// otherwise its workspace is released
+static gp_status tune_rot(gp_plan_s* p, void* scratch, int reps, int* choice) {
+  gp_status st;
+  *choice = 0;
+  launch_fill(p->prec, scratch, p->ntot, 1.0, 0.0, p->stream);
+  if ((st = check_launch(p)) != GP_OK) return st;
+  const double nl = p->d.beta * p->d.dt;
+  const int nrot = [&] { int k = 0; while (find_rot(p->d.n[0], p->prec, k)) ++k; return k; }();
+  // the candidates are timed in alternation, twice each, keeping each one's best
+  // time: the forms differ by ~10 % and clocks drift between measurements
+  std::vector<double> t(1 + nrot, 1e300);
+  gp_status inner = GP_OK;
+  for (int round = 0; round < 2; ++round)
+    for (int v = 0; v <= nrot; ++v) {
+      double us = 0;
+      if (v == 0) {
+        if ((st = time_calls(p, reps, &us, [&] {
+               if (inner == GP_OK) inner = linear_all(p, scratch, TAU_DT, true, nl);
+             })) != GP_OK)
+          return st;
+      } else {
+        if ((st = gp_select_variant(p, 5, v)) != GP_OK) return st;
+        if ((st = time_calls(p, reps, &us, [&] {       // two steps: back in `scratch`
+               if (inner == GP_OK) inner = rot_linear(p, scratch, p->rot.work, TAU_DT, true, nl);
+               if (inner == GP_OK) inner = rot_linear(p, p->rot.work, scratch, TAU_DT, true, nl);
+             })) != GP_OK)
+          return st;
+        us *= 0.5;
+      }
+      if (inner != GP_OK) return inner;
+      t[v] = std::min(t[v], us);
+    }
+  double best = t[0];
+  for (int v = 1; v <= nrot; ++v)
+    if (t[v] < TUNE_TIE * best) { best = t[v]; *choice = v; }
+  return GP_OK;
+}
+
 static gp_status tune_plan(gp_plan_s* p, void* scratch, int reps, std::map<std::string, int>& cache,
                            const std::string& arch, int chosen[5], int runs) {
   gp_status st;
@@ -1695,6 +1866,20 @@ static gp_status tune_plan(gp_plan_s* p, void* scratch, int reps, std::map<std::
       cache[key] = chosen[4];
     }
     if ((st = gp_select_variant(p, 4, chosen[4])) != GP_OK) return st;
+  }
+  // single cubic plans with separate passes: fixed-layout or layout-rotating steps
+  const int n0 = p->d.n[0];
+  if (runs == 1 && !p->plane.on && p->d.n[1] == n0 && p->d.n[2] == n0 && find_rot(n0, p->prec)) {
+    const std::string key = tune_key(arch, p, 5);
+    int c = 0;
+    auto it = cache.find(key);
+    if (it != cache.end() && (it->second == 0 || find_rot(n0, p->prec, it->second - 1))) {
+      c = it->second;
+    } else {
+      if ((st = tune_rot(p, scratch, reps, &c)) != GP_OK) return st;
+      cache[key] = c;
+    }
+    if ((st = gp_select_variant(p, 5, c)) != GP_OK) return st;
   }
   return GP_OK;
 }

@@ -225,3 +225,19 @@ def test_structure_fn_128_against_direct_lag_sums(prec, field):
     print(f"structure function 128^3 {field} {prec}: max error / max S = {err:.2e}")
     assert err < (1e-12 if prec == "c128" else 1e-5)
     plan.close()
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_tg256_rotating_step_against_oracle(tg256, prec):
+    """The 256^3 Taylor-Green workload with layout-rotating linear steps: one Strang
+    step over the whole field against the oracle's literal step."""
+    w, psi0, ref1 = tg256
+    plan = _plan(w["n"], w["alpha"], w["beta"], w["dt"], prec)
+    plan.select_variant(5, 1)
+    dt = torch.complex128 if prec == "c128" else torch.complex64
+    start = psi0.astype(np.complex64).astype(np.complex128) if prec == "c64" else psi0
+    psi = torch.from_numpy(start).to(DEV).to(dt).contiguous()
+    plan.step_n(psi, 1)
+    rel = float(np.linalg.norm(psi.cpu().numpy().astype(np.complex128) - ref1) / np.linalg.norm(ref1))
+    assert rel < (1e-12 if prec == "c128" else 2e-6), rel
+    plan.close()

@@ -387,8 +387,10 @@ def test_autotune_and_cache(tmp_path):
     # three axis schedules, the xy choice (plane pass or separate passes, single run)
     # and, with separate passes, the axis that carries the nonlinear rotation
     assert all(k.split("/")[1] == "c64" for k in data)
-    assert any(k.endswith("/a3/r1") for k in data) and len(chosen) == 5
-    assert len(data) == (5 if chosen[3].startswith("xy: separate") else 4)
+    assert any(k.endswith("/a3/r1") for k in data) and len(chosen) == 6
+    # with separate passes also the nonlinear carrier and the layout form (64^3 has
+    # a rotating schedule)
+    assert len(data) == (6 if chosen[3].startswith("xy: separate") else 4)
     plan2 = _plan(64, 0.3, 4.0, 0.01, "c64")
     assert plan2.autotune(reps=2, cache=cache) == chosen
     psi0 = I.random_field(64, seed=77)
