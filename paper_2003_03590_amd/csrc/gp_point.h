@@ -13,8 +13,7 @@ void launch_mult3(int prec, void* f, int nx, int ny, int nz, const void* mx, con
 void launch_diag_fields(int prec, const void* psi, void* f0, void* f1, void* f2, void* f3, long n, double alpha,
                         double* partial, unsigned blocks, hipStream_t st);
 void launch_spectral(int prec, const void* F0, const void* F1, const void* F2, const void* F3, int nx, int ny, int nz,
-                     double alpha, double beta, int nshell, unsigned blocks, long chunk, double* bins,
-                     hipStream_t st);
+                     double alpha, double beta, int nshell, unsigned blocks, double* bins, hipStream_t st);
 // out[0] = max over the field of |a - b|^2 (partial: blocks doubles)
 void launch_sup_diff2(int prec, const void* a, const void* b, long n, double* partial, unsigned blocks, double* out,
                       hipStream_t st);

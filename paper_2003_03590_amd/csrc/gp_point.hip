@@ -257,50 +257,101 @@ __global__ __launch_bounds__(256) void k_diag_fields(const void* psi, void* f0, 
 // compressible (parallel to k) and incompressible parts, and add 1/2|w^i|^2, 1/2|w^c|^2,
 // 1/2|q|^2, alpha beta |b|^2 to shell round(|k|).  One wavefront per workgroup; bins
 // live in LDS.
+// Shell densities of E_kin^i, E_kin^c, E_q, E_int at one point of the four packed
+// transforms: z = F(k), zm = F(mirror point), (kx, ky, kz) the point's wavenumbers.
+template <class Real>
+__device__ __forceinline__ void spectral_terms(const cplx<Real>* z, const cplx<Real>* zm, int kx, int ky, int kz,
+                                               double inv, double ab, double* d) {
+  // A = (Z + conj Zm)/2, B = (Z - conj Zm)/(2i)
+  const double wxr = 0.5 * ((double)z[0].x + zm[0].x) * inv, wxi = 0.5 * ((double)z[0].y - zm[0].y) * inv;
+  const double wyr = 0.5 * ((double)z[0].y + zm[0].y) * inv, wyi = -0.5 * ((double)z[0].x - zm[0].x) * inv;
+  const double wzr = 0.5 * ((double)z[1].x + zm[1].x) * inv, wzi = 0.5 * ((double)z[1].y - zm[1].y) * inv;
+  const double qxr = 0.5 * ((double)z[1].y + zm[1].y) * inv, qxi = -0.5 * ((double)z[1].x - zm[1].x) * inv;
+  const double qyr = 0.5 * ((double)z[2].x + zm[2].x) * inv, qyi = 0.5 * ((double)z[2].y - zm[2].y) * inv;
+  const double qzr = 0.5 * ((double)z[2].y + zm[2].y) * inv, qzi = -0.5 * ((double)z[2].x - zm[2].x) * inv;
+  const double br = 0.5 * ((double)z[3].x + zm[3].x) * inv, bi = 0.5 * ((double)z[3].y - zm[3].y) * inv;
+  const long k2 = (long)kx * kx + (long)ky * ky + (long)kz * kz;
+  double cr = 0, ci = 0;
+  if (k2 > 0) {
+    const double kdr = kx * wxr + ky * wyr + kz * wzr, kdi = kx * wxi + ky * wyi + kz * wzi;
+    cr = kdr / (double)k2; ci = kdi / (double)k2;
+  }
+  const double cxr = kx * cr, cxi = kx * ci, cyr = ky * cr, cyi = ky * ci, czr = kz * cr, czi = kz * ci;
+  d[1] = 0.5 * (cxr * cxr + cxi * cxi + cyr * cyr + cyi * cyi + czr * czr + czi * czi);
+  const double ixr = wxr - cxr, ixi = wxi - cxi, iyr = wyr - cyr, iyi = wyi - cyi, izr = wzr - czr, izi = wzi - czi;
+  d[0] = 0.5 * (ixr * ixr + ixi * ixi + iyr * iyr + iyi * iyi + izr * izr + izi * izi);
+  d[2] = 0.5 * (qxr * qxr + qxi * qxi + qyr * qyr + qyi * qyi + qzr * qzr + qzi * qzi);
+  d[3] = ab * (br * br + bi * bi);
+}
+
 template <class Real>
 __global__ __launch_bounds__(64) void k_spectral(const void* F0, const void* F1, const void* F2, const void* F3,
                                                  int nx, int ny, int nz, double alpha, double beta, int nshell,
                                                  long chunk, double* __restrict__ bins_partial) {
+  // The four transforms hold pairs of real fields, so the densities at -k equal
+  // those at k (A(-k) = conj A(k), B(-k) = conj B(k), and the Helmholtz parts
+  // follow), in the same shell.  Each pair {k, mirror} is visited once: only the
+  // planes iz = 0 .. nz/2, and in the planes that are their own mirror only the
+  // point of the pair with the smaller index.  The pair counts twice, except that a
+  // point that is its own mirror counts once, and a point with a Nyquist component
+  // (whose mirror index keeps the wavenumber -N/2, so it is not -k) has its mirror
+  // evaluated with the mirror's own wavenumbers.  Each lane takes R consecutive
+  // points along x and adds a shell's terms in registers until the shell changes,
+  // then once into the LDS bins.
+  constexpr int R = 4;
   extern __shared__ double bins[];            // [4][nshell]
   for (int i = threadIdx.x; i < 4 * nshell; i += 64) bins[i] = 0.0;
   __syncthreads();
   const long n = (long)nx * ny * nz;
-  const double inv = 1.0 / (double)n;
+  const long nh = (long)(nz / 2 + 1) * nx * ny;
+  const double inv = 1.0 / (double)n, ab = alpha * beta;
   const long i0 = (long)blockIdx.x * chunk;
-  const long i1 = (i0 + chunk < n) ? i0 + chunk : n;
-  for (long i = i0 + threadIdx.x; i < i1; i += 64) {
-    const int ix = (int)(i % nx), iy = (int)((i / nx) % ny), iz = (int)(i / ((long)nx * ny));
-    const long m = (long)((nz - iz) % nz) * nx * ny + (long)((ny - iy) % ny) * nx + (nx - ix) % nx;
-    const cplx<Real> z0 = ldc<Real>(F0, i), z0m = ldc<Real>(F0, m);
-    const cplx<Real> z1 = ldc<Real>(F1, i), z1m = ldc<Real>(F1, m);
-    const cplx<Real> z2 = ldc<Real>(F2, i), z2m = ldc<Real>(F2, m);
-    const cplx<Real> z3 = ldc<Real>(F3, i), z3m = ldc<Real>(F3, m);
-    // A = (Z + conj Zm)/2, B = (Z - conj Zm)/(2i)
-    const double wxr = 0.5 * ((double)z0.x + z0m.x) * inv, wxi = 0.5 * ((double)z0.y - z0m.y) * inv;
-    const double wyr = 0.5 * ((double)z0.y + z0m.y) * inv, wyi = -0.5 * ((double)z0.x - z0m.x) * inv;
-    const double wzr = 0.5 * ((double)z1.x + z1m.x) * inv, wzi = 0.5 * ((double)z1.y - z1m.y) * inv;
-    const double qxr = 0.5 * ((double)z1.y + z1m.y) * inv, qxi = -0.5 * ((double)z1.x - z1m.x) * inv;
-    const double qyr = 0.5 * ((double)z2.x + z2m.x) * inv, qyi = 0.5 * ((double)z2.y - z2m.y) * inv;
-    const double qzr = 0.5 * ((double)z2.y + z2m.y) * inv, qzi = -0.5 * ((double)z2.x - z2m.x) * inv;
-    const double br = 0.5 * ((double)z3.x + z3m.x) * inv, bi = 0.5 * ((double)z3.y - z3m.y) * inv;
-    const int kx = kfreq(ix, nx), ky = kfreq(iy, ny), kz = kfreq(iz, nz);
-    const long k2 = (long)kx * kx + (long)ky * ky + (long)kz * kz;
-    double cr = 0, ci = 0;
-    if (k2 > 0) {
-      const double kdr = kx * wxr + ky * wyr + kz * wzr, kdi = kx * wxi + ky * wyi + kz * wzi;
-      cr = kdr / (double)k2; ci = kdi / (double)k2;
+  const long i1 = (i0 + chunk < nh) ? i0 + chunk : nh;
+  const void* F[4] = {F0, F1, F2, F3};
+  auto nyq = [](int i, int nn) { return (nn % 2 == 0) && 2 * i == nn; };
+  for (long base = i0 + (long)threadIdx.x * R; base < i1; base += 64L * R) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int cur = -1;
+    for (int r = 0; r < R; ++r) {
+      const long i = base + r;
+      if (i >= i1) break;
+      const int ix = (int)(i % nx), iy = (int)((i / nx) % ny), iz = (int)(i / ((long)nx * ny));
+      const int mx = (nx - ix) % nx, my = (ny - iy) % ny, mz = (nz - iz) % nz;
+      const long m = (long)mz * nx * ny + (long)my * nx + mx;
+      if (m < i) continue;                    // counted with its mirror
+      cplx<Real> z[4], zm[4];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) { z[f] = ldc<Real>(F[f], i); zm[f] = ldc<Real>(F[f], m); }
+      const int kx = kfreq(ix, nx), ky = kfreq(iy, ny), kz = kfreq(iz, nz);
+      double d[4];
+      spectral_terms<Real>(z, zm, kx, ky, kz, inv, ab, d);
+      if (m == i) {
+        // own mirror: once
+      } else if (nyq(ix, nx) || nyq(iy, ny) || nyq(iz, nz)) {
+        double d2[4];
+        spectral_terms<Real>(zm, z, kfreq(mx, nx), kfreq(my, ny), kfreq(mz, nz), inv, ab, d2);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) d[q] += d2[q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) d[q] *= 2.0;
+      }
+      const int s = shell_of((long)kx * kx + (long)ky * ky + (long)kz * kz);
+      if (s != cur) {
+        if (cur >= 0) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) atomicAdd(&bins[q * nshell + cur], acc[q]);
+        }
+        cur = s;
+        acc[0] = acc[1] = acc[2] = acc[3] = 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] += d[q];
     }
-    const double cxr = kx * cr, cxi = kx * ci, cyr = ky * cr, cyi = ky * ci, czr = kz * cr, czi = kz * ci;
-    const double ec = 0.5 * (cxr * cxr + cxi * cxi + cyr * cyr + cyi * cyi + czr * czr + czi * czi);
-    const double ixr = wxr - cxr, ixi = wxi - cxi, iyr = wyr - cyr, iyi = wyi - cyi, izr = wzr - czr, izi = wzi - czi;
-    const double ei = 0.5 * (ixr * ixr + ixi * ixi + iyr * iyr + iyi * iyi + izr * izr + izi * izi);
-    const double eq = 0.5 * (qxr * qxr + qxi * qxi + qyr * qyr + qyi * qyi + qzr * qzr + qzi * qzi);
-    const double eint = alpha * beta * (br * br + bi * bi);
-    const int s = shell_of(k2);
-    atomicAdd(&bins[s], ei);
-    atomicAdd(&bins[nshell + s], ec);
-    atomicAdd(&bins[2 * nshell + s], eq);
-    atomicAdd(&bins[3 * nshell + s], eint);
+    if (cur >= 0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) atomicAdd(&bins[q * nshell + cur], acc[q]);
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < 4 * nshell; i += 64) bins_partial[(long)i * gridDim.x + blockIdx.x] = bins[i];
@@ -804,9 +855,11 @@ void launch_diag_fields(int prec, const void* psi, void* f0, void* f1, void* f2,
     hipLaunchKernelGGL(k_diag_fields<float>, dim3(blocks), dim3(256), 0, st, psi, f0, f1, f2, f3, n, alpha, partial);
 }
 void launch_spectral(int prec, const void* F0, const void* F1, const void* F2, const void* F3, int nx, int ny, int nz,
-                     double alpha, double beta, int nshell, unsigned blocks, long chunk, double* bins,
-                     hipStream_t st) {
+                     double alpha, double beta, int nshell, unsigned blocks, double* bins, hipStream_t st) {
   const size_t sh = sizeof(double) * 4 * (size_t)nshell;
+  // the kernel visits the planes iz = 0 .. nz/2 only (mirror pairs), in `blocks` chunks
+  const long nh = (long)(nz / 2 + 1) * nx * ny;
+  const long chunk = (nh + blocks - 1) / blocks;
   if (prec == P_C128)
     hipLaunchKernelGGL(k_spectral<double>, dim3(blocks), dim3(64), sh, st, F0, F1, F2, F3, nx, ny, nz, alpha, beta,
                        nshell, chunk, bins);

@@ -688,7 +688,7 @@ gp_status diagnose(gp_plan_s* p, const void* psi, void* work) {
   for (void* f : {f0, f1, f2, f3})
     if ((st = fwd3_unnorm(p, f)) != GP_OK) return st;
   launch_spectral(p->prec, f0, f1, f2, f3, p->d.n[0], p->d.n[1], p->d.n[2], p->d.alpha, p->d.beta, p->nshell,
-                  p->spec_blocks, p->spec_chunk, p->bins_part, p->stream);
+                  p->spec_blocks, p->bins_part, p->stream);
   if ((st = check_launch(p)) != GP_OK) return st;
   // fixed-order reductions of every partial into red = [kin_x, kin_y, kin_z, field[3], spectra[4][nshell]]
   const double nt = (double)p->ntot;

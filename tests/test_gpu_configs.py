@@ -70,8 +70,8 @@ def _ensemble_inputs(runs, K):
 
 def test_ensemble_workload_48_runs():
     """48 smoothed-random-phase runs (32 at 64^3, 16 at 96^3), complex64, dt = 1e-3,
-    300 steps in one graph launch: every run against its own complex128 run, and
-    per-run mass/energy drift stated."""
+    300 steps in one graph launch: every run within 1e-5 of its own complex128 run,
+    and per-run mass/energy drift stated."""
     import paper_2003_03590_amd as gp
     w = I.WORKLOADS["ens48"]
     runs = [dict(r, dt=w["dt"]) for r in w["runs"]]
@@ -93,7 +93,7 @@ def test_ensemble_workload_48_runs():
         p.close()
     print(f"ensemble: max dN {dN.max():.2e}, max dE {dE.max():.2e}, max rel-L2 vs c128 {max(rels):.2e}")
     assert dN.max() < 1e-5 and dE.max() < 1e-4
-    assert max(rels) < 1e-4
+    assert max(rels) < 1e-5          # the complex64 target in psi
 
 
 def test_ensemble_run_against_oracle():
