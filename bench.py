@@ -210,14 +210,17 @@ def large_form(gp, torch, I, steps=5):
         torch.cuda.synchronize()
         axis["xyz"[ax]] = per_launch / (a.elapsed_time(b) / 3 / 1e3) / 1e9
     x = torch.empty_like(psi)
-    x.copy_(psi)
-    torch.cuda.synchronize()
-    a.record(st)
-    for _ in range(3):
-        x.copy_(psi)
-    b.record(st)
-    torch.cuda.synchronize()
-    copy_gbs = per_launch / (a.elapsed_time(b) / 3 / 1e3) / 1e9
+    copies = {}
+    for name, fn in (("gp_copy_state", lambda: plan.copy_state(psi, x)), ("torch_copy", lambda: x.copy_(psi))):
+        fn()
+        torch.cuda.synchronize()
+        a.record(st)
+        for _ in range(3):
+            fn()
+        b.record(st)
+        torch.cuda.synchronize()
+        copies[name] = per_launch / (a.elapsed_time(b) / 3 / 1e3) / 1e9
+    copy_gbs = copies["gp_copy_state"]
     del x
     # both forms of the linear steps, whichever the autotuner kept (fixed layout in
     # place, or layout-rotating passes through one more state)
@@ -235,18 +238,28 @@ def large_form(gp, torch, I, steps=5):
         forms[name] = {"ms_per_step": fms / steps,
                        "axis_pass_gbs": per_launch * launches / (fms / 1e3) / 1e9,
                        "frac": per_launch * launches / (fms / 1e3) / 1e9 / HBM_PEAK_GBS}
-    plan.select_variant(5, 1 if chosen.startswith("layout: rotating") else 0)
+    rot = chosen.startswith("layout: rotating")
+    plan.select_variant(5, 1 if rot else 0)
     out = {"workload": "rvr1024: 1024^3 complex64, 40 random vortex-ring pairs (seed 1), dt = 2.5e-4",
            "steps": steps, "ms_per_step": ms / steps,
            "value": float(n) ** 3 * steps / (ms / 1e3), "unit": "grid-point.steps/s",
            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": gbs / HBM_PEAK_GBS, "per_launch_bytes": per_launch,
-                        "traffic": pass_traffic("axis_pass_rvr1024_traffic.json",
-                                                [plan.schedule(ax) for ax in range(3)]),
-                        "traffic_source": "profiles/axis_pass_rvr1024_traffic.json (null once the kernel "
-                                          "sources or schedules differ from the profiled ones)",
+                        "kernel": ("rot_pass (layout-rotating propagator pass; the nonlinear rotation fused "
+                                   "into the first pass of each step)") if rot else
+                                  ("axis_pass (propagator; the nonlinear rotation fused into the carrier "
+                                   "axis's pass)"),
+                        "per_launch": "one axis pass: reads and writes the whole state once (2 N^3 S bytes)",
+                        "traffic": (pass_traffic("rot_pass_rvr1024_traffic.json") if rot else
+                                    pass_traffic("axis_pass_rvr1024_traffic.json",
+                                                 [plan.schedule(ax) for ax in range(3)])),
+                        "traffic_source": "profiles/%s_pass_rvr1024_traffic.json (null once the kernel "
+                                          "sources or schedules differ from the profiled ones)"
+                                          % ("rot" if rot else "axis"),
                         "mean_launch_us": ms * 1e3 / launches,
                         "copy_gbs": copy_gbs, "frac_of_copy": gbs / copy_gbs,
+                        "copy": "gp_copy_state: read 8 GiB, write 8 GiB, one 16-byte unit per lane "
+                                f"(torch's copy_ of the same tensors: {copies['torch_copy']:.0f} GB/s)",
                         "axis_gbs": axis, "axis_frac": {k: v / HBM_PEAK_GBS for k, v in axis.items()},
                         "axis_frac_of_copy": {k: v / copy_gbs for k, v in axis.items()}},
            "layout_forms": forms,
@@ -300,12 +313,14 @@ def argle_form(gp, torch, I, steps=200, warmup=20):
     return out
 
 
-def passes_mode(gp, torch, spec, reps, tune=False, variants=None):
+def passes_mode(gp, torch, spec, reps, tune=False, variants=None, rotating=False):
     """Each axis pass (propagator sub-step S(s, L_j)) `reps` times on a random
-    N^3 field, then `reps` device copies of the same bytes (calibration of the
-    FETCH_SIZE / WRITE_SIZE counters); prints one JSON line of event timings.
-    With `tune`, the schedules are autotuned first; `variants` (one schedule
-    variant per axis) fixes them instead, e.g. to those a timed run selected."""
+    N^3 field, then `reps` plain device copies of the same bytes (gp_copy_state:
+    the bandwidth reference, and the calibration of the FETCH_SIZE / WRITE_SIZE
+    counters); prints one JSON line of event timings.  With `tune`, the schedules
+    are autotuned first; `variants` (one schedule variant per axis) fixes them
+    instead, e.g. to those a timed run selected.  With `rotating`, the passes are
+    the layout-rotating ones: `reps` calls of one Strang step (six passes)."""
     n, prec = spec.split(":")
     n = int(n)
     plan = gp.Plan(n, 0.05, 40.0, 1e-3, prec)
@@ -314,32 +329,37 @@ def passes_mode(gp, torch, spec, reps, tune=False, variants=None):
     if variants:
         for ax, v in enumerate(int(x) for x in variants.split(",")):
             plan.select_variant(ax, v)
+    if rotating:
+        plan.select_variant(5, 1)
     dt = torch.complex128 if prec == "c128" else torch.complex64
     S = 16 if prec == "c128" else 8
     psi = torch.randn(n, n, n, dtype=dt, device="cuda")
+    psi /= psi.abs()
     st = torch.cuda.current_stream()
     out = {"n": n, "prec": prec, "bytes_per_launch": 2 * n ** 3 * S,
-           "schedule": [plan.schedule(ax) for ax in range(3)]}
-    for ax in range(3):
-        plan.substep_linear(psi, ax, 1e-3)
+           "schedule": [plan.schedule(ax) for ax in range(6)]}
+
+    def timed(fn, k):
+        fn()
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(st)
-        for _ in range(reps):
-            plan.substep_linear(psi, ax, 1e-3)
+        for _ in range(k):
+            fn()
         b.record(st)
         torch.cuda.synchronize()
-        us = a.elapsed_time(b) / reps * 1e3
-        out[f"axis{ax}_us"] = us
-        out[f"axis{ax}_GBs"] = 2 * n ** 3 * S / us / 1e3
+        return a.elapsed_time(b) / k * 1e3
+    if rotating:
+        us = timed(lambda: plan.step_n(psi, 1), reps) / 6
+        out["rot_us"] = us
+        out["rot_GBs"] = 2 * n ** 3 * S / us / 1e3
+    else:
+        for ax in range(3):
+            us = timed(lambda: plan.substep_linear(psi, ax, 1e-3), reps)
+            out[f"axis{ax}_us"] = us
+            out[f"axis{ax}_GBs"] = 2 * n ** 3 * S / us / 1e3
     x = torch.empty_like(psi)
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record(st)
-    for _ in range(reps):
-        x.copy_(psi)
-    b.record(st)
-    torch.cuda.synchronize()
-    us = a.elapsed_time(b) / reps * 1e3
+    us = timed(lambda: plan.copy_state(psi, x), reps)
     out["copy_us"] = us
     out["copy_GBs"] = 2 * n ** 3 * S / us / 1e3
     print(json.dumps(out))
@@ -385,6 +405,7 @@ def main(argv=None):
                          "and one device copy of the same bytes, then exit")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--tune", action="store_true", help="with --passes: autotune the schedules first")
+    ap.add_argument("--rotating", action="store_true", help="with --passes: the layout-rotating passes")
     ap.add_argument("--variants", default=None, metavar="VX,VY,VZ",
                     help="with --passes: schedule variant of each axis (as reported by a timed run)")
     a = ap.parse_args(argv)
@@ -400,7 +421,7 @@ def main(argv=None):
     import paper_2003_03590_amd as gp
 
     if a.passes:
-        return passes_mode(gp, torch, a.passes, a.reps, tune=a.tune, variants=a.variants)
+        return passes_mode(gp, torch, a.passes, a.reps, tune=a.tune, variants=a.variants, rotating=a.rotating)
     if a.argle:
         print(json.dumps(argle_form(gp, torch, I)))
         return 0
@@ -441,10 +462,10 @@ def main(argv=None):
         "value_step_only": step_only,
         "hbm_gbs_per_split_step": 6.0 * npts * S / (sum(f64["step_ms"]) / 1e3 / split_steps) / 1e9,
         "bytes_per_split_step_min": 6.0 * npts * S,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "roofline_tg256_c128": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "cache_resident": "the 256 MiB state fits the 256 MB last-level cache; the HBM-bound "
-                                       "form is large_1024_c64.roofline",
+                                       "form (the line's roofline) is the 1024^3 complex64 pass",
                      "traffic": pass_traffic(schedules=[f64["plan"].schedule(ax) for ax in range(3)]),
                      "kernel": "axis_pass (propagator; the nonlinear rotation fused into the carrier axis's pass), "
                                "mean of the three",
@@ -468,6 +489,11 @@ def main(argv=None):
         res["ensemble"] = ensemble_form(gp, torch, I)
     if not a.no_large:
         res["large_1024_c64"] = large_form(gp, torch, I)
+        # the HBM roofline: the axis pass on a state 32x the last-level cache
+        res["roofline"] = dict(res["large_1024_c64"]["roofline"],
+                               workload="rvr1024: 1024^3 complex64, timed inside large_1024_c64")
+    else:
+        res["roofline"] = res["roofline_tg256_c128"]
     if not a.no_cpu_baseline:
         res["cpu_baseline"] = oracle_sample(psi0, w)
     print(json.dumps(res))

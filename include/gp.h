@@ -145,6 +145,13 @@ GP_API gp_status gp_step_literal_n(gp_plan_t* p, void* psi, int64_t nsteps);
  * dir = +1 inverse without factor.  Natural fftfreq order of k.  in may equal out. */
 GP_API gp_status gp_fft3(gp_plan_t* p, const void* in, void* out, int32_t dir);
 
+/* Bandwidth reference, not part of the method: dst <- src for one state of the plan
+ * (n0 n1 n2 complex points, device pointers, 16-byte aligned, not overlapping),
+ * one 16-byte unit per lane, on the plan's stream.  Timing it gives what HBM
+ * delivers to a plain read-once, write-once stream of the bytes an axis pass moves.
+ * GP_ERR_ARG for a null pointer, GP_ERR_STATE for a batch plan. */
+GP_API gp_status gp_copy_state(gp_plan_t* p, const void* src, void* dst);
+
 /* Mass, energy and its decomposition (see gp_energy).  work: dev, gp_work_bytes.
  * Synchronizes.  GP_ERR_NONFINITE if any value is NaN/Inf. */
 GP_API gp_status gp_energies(gp_plan_t* p, const void* psi, void* work, gp_energy* out);

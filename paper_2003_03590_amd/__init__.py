@@ -158,6 +158,12 @@ class Plan:
         _check(lib().gp_fft3(self._h, self._field(x, "in"), self._field(out, "out"), int(direction)))
         return out
 
+    def copy_state(self, src, out=None):
+        """Plain device copy of one state (the bandwidth reference of the passes)."""
+        out = self.empty() if out is None else out
+        _check(lib().gp_copy_state(self._h, self._field(src, "in"), self._field(out, "out")))
+        return out
+
     def energies(self, psi) -> dict:
         e = gp_energy()
         _check(lib().gp_energies(self._h, self._field(psi), C.c_void_p(_ptr(self.work())), C.byref(e)))

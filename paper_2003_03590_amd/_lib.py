@@ -57,6 +57,7 @@ SIGNATURES = {
     "gp_step_n": (ST, [P, P, C.c_int64]),
     "gp_step_literal_n": (ST, [P, P, C.c_int64]),
     "gp_fft3": (ST, [P, P, P, C.c_int32]),
+    "gp_copy_state": (ST, [P, P, P]),
     "gp_energies": (ST, [P, P, P, C.POINTER(gp_energy)]),
     "gp_energies_static": (ST, [P, P, C.POINTER(gp_energy)]),
     "gp_spectra": (ST, [P, P, P, C.POINTER(C.c_double), C.c_int32, C.POINTER(gp_energy)]),

@@ -254,6 +254,58 @@ __device__ __forceinline__ void inverse_all(cplx<Real>* v, cplx<Real>* lds, int 
   }
 }
 
+// Complex64 tiles of whole contiguous pencils move between global memory and the
+// lanes through the LDS exchange buffer with 16-byte accesses: unit u of the tile
+// (u = tid + THREADS i) holds points 2q, 2q+1 of tile pencil u / (N/2), so one load or
+// store instruction of a wavefront covers 1 KB of one pencil, against four 128-byte
+// pieces of four pencils with one point per lane.  `pencil(pc)` is the element offset
+// of tile pencil pc.  Complex128 points are 16 bytes already and move directly.
+template <class S>
+constexpr bool wide_io() { return S::NS > 1 && S::N % 2 == 0 && S::E % 2 == 0; }
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <class S, class F>
+__device__ __forceinline__ void load_tile_wide(cplx<float>* v, cplx<float>* lds, const void* in, F pencil,
+                                               int t, int col) {
+  using L = Lds<S, 8, CONTIG>;
+  constexpr int HN = S::N / 2, U = S::E / 2;
+  const auto src = gptr<cplx<float>>(in);
+  f32x4 r[U];
+#pragma unroll
+  for (int i = 0; i < U; ++i) {
+    const int u = (int)threadIdx.x + S::THREADS * i, pc = u / HN, q = u % HN;
+    r[i] = *(const GPK_GLOBAL f32x4*)(src + pencil(pc) + 2 * q);
+  }
+#pragma unroll
+  for (int i = 0; i < U; ++i) {
+    const int u = (int)threadIdx.x + S::THREADS * i, pc = u / HN, q = u % HN;
+    lds[L::addr(2 * q, pc)] = mk(r[i].x, r[i].y);
+    lds[L::addr(2 * q + 1, pc)] = mk(r[i].z, r[i].w);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) v[e] = lds[L::addr(t + S::T * e, col)];
+}
+
+template <class S, class F>
+__device__ __forceinline__ void store_tile_wide(const cplx<float>* v, cplx<float>* lds, void* out, F pencil,
+                                                int t, int col) {
+  using L = Lds<S, 8, CONTIG>;
+  constexpr int HN = S::N / 2, U = S::E / 2;
+  const auto dst = gptr_mut<cplx<float>>(out);
+  __syncthreads();                          // the last exchange has been read
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) lds[L::addr(t + S::T * e, col)] = v[e];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < U; ++i) {
+    const int u = (int)threadIdx.x + S::THREADS * i, pc = u / HN, q = u % HN;
+    const cplx<float> p0 = lds[L::addr(2 * q, pc)], p1 = lds[L::addr(2 * q + 1, pc)];
+    *(GPK_GLOBAL f32x4*)(dst + pencil(pc) + 2 * q) = f32x4{p0.x, p0.y, p1.x, p1.y};
+  }
+}
+
 // nonlinear sub-step S(dt, N): v <- v exp(-i beta (|v|^2 - 1) dt), in the working precision
 template <class Real>
 __device__ __forceinline__ cplx<Real> nl_rotate(cplx<Real> v, double coef) {
@@ -346,6 +398,16 @@ __global__ __launch_bounds__(S::THREADS) void axis_pass(PassArgs a) {
     for (int e = 0; e < E; ++e) v[e] = *(const GPK_GLOBAL C*)(inb + e * estep + w.loff);
   };
 
+  // x pencils of complex64 propagator passes: whole tiles of contiguous pencils,
+  // moved with 16-byte accesses (a pencil past the last one takes the last one, as
+  // the lanes do, so the duplicate stores write equal bytes)
+  constexpr bool WIDE = sizeof(Real) == 4 && KIND == CONTIG && MODE == PROP &&
+                        (PRO == PRO_NONE || PRO == PRO_NL) && wide_io<S>();
+  auto tile_pencil = [&](int pc) {
+    const long p = tile * W + pc;
+    return (p < a.npencils ? p : a.npencils - 1) * (long)S::N;
+  };
+
   double kin_acc = 0.0;
   // transform one tile held in v (prologue, transform, multiplier, inverse) and store it
   auto process = [&](C* v, const Where& cur) {
@@ -422,14 +484,19 @@ __global__ __launch_bounds__(S::THREADS) void axis_pass(PassArgs a) {
       }
     }
 
-    const auto outb = gptr_mut<char>(a.out) + cur.bbase * (long)sizeof(C);
+    if constexpr (WIDE) {
+      store_tile_wide<S>(v, lds, a.out, tile_pencil, t, col);
+    } else {
+      const auto outb = gptr_mut<char>(a.out) + cur.bbase * (long)sizeof(C);
 #pragma unroll
-    for (int e = 0; e < E; ++e) *(GPK_GLOBAL C*)(outb + e * estep + cur.loff) = v[e];
+      for (int e = 0; e < E; ++e) *(GPK_GLOBAL C*)(outb + e * estep + cur.loff) = v[e];
+    }
   };
 
   C v[E];
   const Where w = where(tile);
-  load(v, w);
+  if constexpr (WIDE) load_tile_wide<S>(v, lds, a.in, tile_pencil, t, col);
+  else load(v, w);
   process(v, w);
 
   if constexpr (PRO == PRO_KIN) {

@@ -26,6 +26,7 @@ void launch_mach_partials(int prec, const void* psi, const void* d0, const void*
 void launch_segmax(const double* in, long len, double* out, hipStream_t st);
 // every point of f <- re + i im
 void launch_fill(int prec, void* f, long n, double re, double im, hipStream_t st);
+void launch_copy16(const void* src, void* dst, long bytes, hipStream_t st);   // bytes: a multiple of 8
 // helicity stages (see the kernels for the packing of real fields into states)
 // partial: blocks doubles (sum |grad psi|^2)
 void launch_hel_pack(int prec, const void* psi, const void* d0, const void* d1, const void* d2, void* s3, void* s4,

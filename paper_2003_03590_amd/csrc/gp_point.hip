@@ -823,6 +823,16 @@ __global__ __launch_bounds__(256) void k_fill(void* f, unsigned n, double re, do
   if (i < n) stc<Real>(f, i, re, im);
 }
 
+// plain stream copy, one 16-byte unit per lane (the bandwidth reference of the passes);
+// an odd 8-byte tail goes with the first lane
+__global__ __launch_bounds__(256) void k_copy16(const void* __restrict__ src, void* __restrict__ dst, long units,
+                                                int tail8) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i < units) ((f4*)dst)[i] = ((const f4*)src)[i];
+  if (tail8 && i == 0) ((double*)dst)[2 * units] = ((const double*)src)[2 * units];
+}
+
 // ----------------------------------------------------------------- launch wrappers
 static unsigned grid_for(long n, int threads, unsigned cap = 4096) {
   long g = (n + threads - 1) / threads;
@@ -988,6 +998,11 @@ void launch_hel_spectral(int prec, const void* V01, const void* V2, const void* 
 void launch_fill(int prec, void* f, long n, double re, double im, hipStream_t st) {
   if (prec == P_C128) hipLaunchKernelGGL(k_fill<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, f, (unsigned)n, re, im);
   else hipLaunchKernelGGL(k_fill<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, f, (unsigned)n, re, im);
+}
+void launch_copy16(const void* src, void* dst, long bytes, hipStream_t st) {
+  const long units = bytes / 16;
+  const unsigned grid = (unsigned)std::max(1L, (units + 255) / 256);
+  hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, st, src, dst, units, (int)((bytes % 16) != 0));
 }
 void launch_segmax(const double* in, long len, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_segmax, dim3(1), dim3(256), 0, st, in, len, out);

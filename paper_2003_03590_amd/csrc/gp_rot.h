@@ -11,6 +11,9 @@
 // layout [z][y][x] -> [y][x][z] -> [x][z][y] -> [z][y][x]: no access ever has the
 // N^2 stride of a z pencil in the fixed layout, whose rows each fall in their own
 // memory page.  The passes are out of place (a second state of workspace).
+// Complex64 tiles are read with 16-byte loads staged through LDS (load_tile_wide);
+// the turned rows are written one point per lane, which measured faster than
+// 16-byte stores of the same 64-byte row pieces.
 #pragma once
 
 #include "gp_pass.h"
@@ -51,10 +54,14 @@ __global__ __launch_bounds__(S::THREADS) void rot_pass(RotArgs a) {
   constexpr int TL = (T * SZ <= 128) ? T : 128 / SZ;
   const int t = tid % TL + TL * (tid / (TL * W));
   const int col = (tid / TL) % W;
-  const auto in = gptr<C>(a.in) + (a0 + col) * NN + b * N + t;
   C v[E];
+  if constexpr (sizeof(Real) == 4 && wide_io<S>()) {
+    load_tile_wide<S>(v, lds, a.in, [&](int pc) { return (a0 + pc) * NN + b * N; }, t, col);
+  } else {
+    const auto in = gptr<C>(a.in) + (a0 + col) * NN + b * N + t;
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = in[T * e];
+    for (int e = 0; e < E; ++e) v[e] = in[T * e];
+  }
 
   if constexpr (PRO == PRO_NL) {
 #pragma unroll

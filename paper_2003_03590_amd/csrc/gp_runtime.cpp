@@ -1021,6 +1021,14 @@ gp_status gp_fft3(gp_plan_t* p, const void* in, void* out, int32_t dir) {
   return fft3(p, in, out, dir);
 }
 
+gp_status gp_copy_state(gp_plan_t* p, const void* src, void* dst) {
+  gp_status st = usable_single(p);
+  if (st != GP_OK) return st;
+  if (!src || !dst) return fail(GP_ERR_ARG, "null field");
+  launch_copy16(src, dst, p->ntot * (p->prec == P_C128 ? 16L : 8L), p->stream);
+  return check_launch(p);
+}
+
 gp_status gp_energies(gp_plan_t* p, const void* psi, void* work, gp_energy* out) {
   gp_status st = usable_single(p);
   if (st != GP_OK) return st;
@@ -1712,6 +1720,14 @@ static gp_status time_calls(gp_plan_s* p, int reps, double* us, const std::funct
 // variant index, the first axis, separate passes), so that repeated tunings agree.
 constexpr double TUNE_TIE = 0.99;
 
+// With GP_TUNE_LOG set, every timed candidate is reported on stderr.
+static void tune_note(const gp_plan_s* p, const char* what, int axis, int cand, double us) {
+  static const bool on = getenv("GP_TUNE_LOG") != nullptr;
+  if (on)
+    fprintf(stderr, "gp_autotune %dx%dx%d %s axis %d candidate %d: %.1f us\n", p->d.n[0], p->d.n[1], p->d.n[2],
+            what, axis, cand, us);
+}
+
 static gp_status tune_xy(gp_plan_s* p, void* scratch, int reps, int runs, int* choice) {
   gp_status st;
   *choice = 0;
@@ -1768,6 +1784,7 @@ static gp_status tune_nl(gp_plan_s* p, void* scratch, int reps, int* choice) {
          })) != GP_OK)
       return st;
     if (inner != GP_OK) return inner;
+    tune_note(p, "nonlinear on", a, a, us);
     if (us < TUNE_TIE * best) { best = us; *choice = a; }
   }
   return GP_OK;
@@ -1805,6 +1822,7 @@ static gp_status tune_rot(gp_plan_s* p, void* scratch, int reps, int* choice) {
         us *= 0.5;
       }
       if (inner != GP_OK) return inner;
+      tune_note(p, "layout", 5, v, us);
       t[v] = std::min(t[v], us);
     }
   double best = t[0];
@@ -1834,6 +1852,7 @@ static gp_status tune_plan(gp_plan_s* p, void* scratch, int reps, std::map<std::
       if ((st = gp_select_variant(p, a, v)) != GP_OK) return st;
       double us = 0;
       if ((st = time_axis(p, a, scratch, reps, &us)) != GP_OK) return st;
+      tune_note(p, "schedule", a, v, us);
       if (us < TUNE_TIE * best) { best = us; bestv = v; }
     }
     if ((st = gp_select_variant(p, a, bestv)) != GP_OK) return st;

@@ -432,3 +432,17 @@ def test_nonlinear_carrier_axis(prec):
     with pytest.raises(gp._lib.GPError):
         flat.select_variant(4, 2)            # axis of length 1
     flat.close()
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("shape", [(3, 5, 7), (16, 16, 16), (64, 32, 8)], ids=lambda s: "x".join(map(str, s)))
+def test_copy_state_is_exact(shape, prec):
+    """gp_copy_state (the bandwidth reference): a bit-exact copy, including the odd
+    8-byte tail of a complex64 state with an odd point count."""
+    plan = _plan(shape, 0.05, 40.0, 1e-3, prec)
+    rng = np.random.default_rng(3)
+    x = _to_dev(rng.standard_normal(shape) + 1j * rng.standard_normal(shape), prec)
+    y = plan.copy_state(x)
+    torch.cuda.synchronize()
+    assert torch.equal(torch.view_as_real(y), torch.view_as_real(x))
+    plan.close()
