@@ -112,9 +112,9 @@ def run_form(gp, torch, psi0_np, w, prec, steps, warmup, tune=True):
 def literal_form(torch, plan, psi0_np, step_ms_merged, steps=10):
     """The literal (un-merged) Strang step of the time-evolution section on the same
     plan and field: per step two 3-D linear half steps, each a forward 3-D FFT
-    (3 passes), the 3-D multiplier and an inverse 3-D FFT (3 passes), with the
-    nonlinear rotation between them: 30 N^3 S bytes per step against the merged
-    form's 6 N^3 S."""
+    (3 passes, the last applying the 3-D multiplier before it stores) and an
+    inverse 3-D FFT (3 passes), with the nonlinear rotation between them: 13 sweeps,
+    26 N^3 S bytes per step against the merged form's 6 N^3 S."""
     S = 16 if plan.prec == 0 else 8
     dt = torch.complex128 if S == 16 else torch.complex64
     psi = torch.from_numpy(psi0_np).to("cuda").to(dt).contiguous()
@@ -128,7 +128,7 @@ def literal_form(torch, plan, psi0_np, step_ms_merged, steps=10):
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / steps
     npts = float(psi0_np.size)
-    per_step = 30.0 * npts * S
+    per_step = 26.0 * npts * S
     return {"steps": steps, "ms_per_step": ms, "value": npts / (ms / 1e3), "unit": "grid-point.steps/s",
             "bytes_per_step": per_step, "hbm_gbs": per_step / (ms / 1e3) / 1e9,
             "merged_over_literal": ms / step_ms_merged}

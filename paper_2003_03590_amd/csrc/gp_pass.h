@@ -47,8 +47,10 @@ enum PassMode { PROP = 0, FWD = 1, INV = 2 };
 // pointwise work fused in front of the transform (PRO_KIN: none, but accumulate
 // sum k_j^2 |F_j v|^2 after the forward transform for the kinetic energy;
 // PRO_ARGLE: none, but turn the derivative after the inverse transform into the
-// explicit part of the imaginary-time step)
-enum Prologue { PRO_NONE = 0, PRO_NL = 1, PRO_ADJ_NL = 2, PRO_DENSITY = 3, PRO_KIN = 4, PRO_ARGLE = 5 };
+// explicit part of the imaginary-time step; PRO_MULT3: none, but multiply the
+// forward transform by the separable 3-D propagator m_x(k_x) m_y(k_y) m_z(k_z) before
+// it is stored -- the last forward pass of the literal 3-D form)
+enum Prologue { PRO_NONE = 0, PRO_NL = 1, PRO_ADJ_NL = 2, PRO_DENSITY = 3, PRO_KIN = 4, PRO_ARGLE = 5, PRO_MULT3 = 6 };
 
 // per-run pointers of a grouped (ensemble) launch: run = blockIdx.y
 struct RunPtrs {
@@ -65,9 +67,10 @@ struct PassArgs {
   void* out;               // output field (may equal in)
   const void* mult;        // PROP: multiplier in lane order (N_j FP64 complex entries)
   const void* tw;          // per-stage twiddles W_{R M}^{lo k} (Tab<Real> entries, layout above)
-  const void* aux;         // PRO_ADJ_NL, PRO_ARGLE: the state phi at the same points
-  const void* aux2;        // PRO_ARGLE: d phi / dx and d phi / dy at the same points
-  const void* aux3;
+  const void* aux;         // PRO_ADJ_NL, PRO_ARGLE: the state phi at the same points;
+                           // PRO_MULT3: m_x in natural frequency order (FP64 complex)
+  const void* aux2;        // PRO_ARGLE: d phi / dx and d phi / dy at the same points;
+  const void* aux3;        // PRO_MULT3: m_y and m_z
   const void* vel;         // PRO_ARGLE: velocity planes v_x, v_y, v_z (Real, one field each)
   double q4a;              // PRO_ARGLE: 1 / (4 alpha)
   const double* ksq;       // k_j^2 in position order (kinetic accumulation)
@@ -77,6 +80,8 @@ struct PassArgs {
   long npencils;           // number of pencils along this axis
   long inner, outer;       // pencil p starts at (p / inner) * outer + (p % inner)
   long es;                 // element stride along the axis
+  int axis;                // PRO_MULT3: the pass's axis (0 x, 1 y, 2 z) ...
+  int nx, ny;              // ... and the grid's x and y lengths
 };
 
 template <int N_, int T_, int W_, int R0, int R1, int R2>
@@ -379,7 +384,7 @@ __global__ __launch_bounds__(S::THREADS) void axis_pass(PassArgs a) {
   // transforms and stores exactly what that pencil's own lanes do, so every load and
   // store is issued unconditionally (no branch around memory instructions) and the
   // duplicate stores write equal bytes.
-  struct Where { long bbase; unsigned loff; bool active; };
+  struct Where { long bbase; unsigned loff; bool active; long pstart; };
   auto where = [&](long tl) {
     Where w;
     const long p = tl * W + col;
@@ -389,6 +394,7 @@ __global__ __launch_bounds__(S::THREADS) void axis_pass(PassArgs a) {
     // (no 64-bit division subroutine with its branches)
     const unsigned inner = (unsigned)a.inner, q0 = (unsigned)(tl * W), q = (unsigned)pp;
     w.bbase = (long)(q0 / inner) * a.outer + (long)(q0 % inner);
+    w.pstart = (long)(q / inner) * a.outer + (long)(q % inner);
     w.loff = (unsigned)(((long)(q / inner) * a.outer + (long)(q % inner) - w.bbase + (long)t * es) * (long)sizeof(C));
     return w;
   };
@@ -481,6 +487,22 @@ __global__ __launch_bounds__(S::THREADS) void axis_pass(PassArgs a) {
         const Real sc = Real(a.scale);
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = cscale(v[e], sc);
+        if constexpr (PRO == PRO_MULT3) {
+          // v[e] holds frequency t + T e of the pencil starting at point cur.pstart;
+          // the factors multiply in the order (m_x m_y) m_z, in FP64
+          const auto mx = gptr<cplx<double>>(a.aux), my = gptr<cplx<double>>(a.aux2),
+                     mz = gptr<cplx<double>>(a.aux3);
+          const long nxy = (long)a.nx * a.ny;
+          const int ix = (int)(cur.pstart % a.nx), iy = (int)((cur.pstart / a.nx) % a.ny),
+                    iz = (int)(cur.pstart / nxy);
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            const int f = t + T * e;
+            const cplx<double> m = cmul(cmul(mx[a.axis == 0 ? f : ix], my[a.axis == 1 ? f : iy]),
+                                        mz[a.axis == 2 ? f : iz]);
+            v[e] = pmul(v[e], m);
+          }
+        }
       }
     }
 
@@ -523,6 +545,7 @@ void launch_pass(const PassArgs& a, unsigned grid, unsigned runs, hipStream_t st
 }
 
 // kernel variants compiled for every schedule
-enum Variant { V_PROP = 0, V_PROP_NL, V_PROP_ADJ, V_PROP_KIN, V_FWD, V_FWD_DENSITY, V_INV, V_PROP_ARGLE, V_COUNT };
+enum Variant { V_PROP = 0, V_PROP_NL, V_PROP_ADJ, V_PROP_KIN, V_FWD, V_FWD_DENSITY, V_INV, V_PROP_ARGLE, V_FWD_MULT3,
+               V_COUNT };
 
 }  // namespace gpk

@@ -61,6 +61,7 @@ void fill(PassEntry& e) {
   e.fn[KIND][V_FWD_DENSITY] = &launch_pass<Real, S, KIND, FWD, PRO_DENSITY>;
   e.fn[KIND][V_INV] = &launch_pass<Real, S, KIND, INV, PRO_NONE>;
   e.fn[KIND][V_PROP_ARGLE] = &launch_pass<Real, S, KIND, PROP, PRO_ARGLE>;
+  e.fn[KIND][V_FWD_MULT3] = &launch_pass<Real, S, KIND, FWD, PRO_MULT3>;
 }
 
 template <class Real, class S>

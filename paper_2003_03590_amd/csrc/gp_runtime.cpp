@@ -649,6 +649,27 @@ gp_status fwd3_unnorm(gp_plan_s* p, void* f) {
     if ((st = pass(p, a, V_FWD, f, f, nullptr, 0.0, nullptr, 1.0)) != GP_OK) return st;
   return GP_OK;
 }
+// unnormalised forward 3-D transform in place, the last pass multiplying by the 3-D
+// propagator exp(-i alpha |k|^2 tau)/N^3 = m_x(k_x) m_y(k_y) m_z(k_z) before it stores
+gp_status fwd3_mult3(gp_plan_s* p, void* f, int tau) {
+  gp_status st;
+  int last = -1;
+  for (int a = 0; a < 3; ++a) if (p->ax[a].n > 1) last = a;
+  for (int a = 0; a < last; ++a)
+    if ((st = pass(p, a, V_FWD, f, f, nullptr, 0.0, nullptr, 1.0)) != GP_OK) return st;
+  if (last < 0) {               // 1x1x1 grid: the multiplier alone
+    launch_mult3(p->prec, f, 1, 1, 1, p->ax[0].nat[tau], p->ax[1].nat[tau], p->ax[2].nat[tau], p->stream);
+    return check_launch(p);
+  }
+  const Axis& A = p->ax[last];
+  PassArgs g{};
+  g.in = f; g.out = f; g.tw = A.tw; g.scale = 1.0;
+  g.aux = p->ax[0].nat[tau]; g.aux2 = p->ax[1].nat[tau]; g.aux3 = p->ax[2].nat[tau];
+  g.npencils = A.npencils; g.inner = A.inner; g.outer = A.outer; g.es = A.es;
+  g.axis = last; g.nx = p->d.n[0]; g.ny = p->d.n[1];
+  A.e->fn[A.kind][V_FWD_MULT3](g, A.blocks, 1, p->stream);
+  return check_launch(p);
+}
 gp_status inv3_unnorm(gp_plan_s* p, void* f) {
   gp_status st;
   for (int a = 0; a < 3; ++a)
@@ -999,10 +1020,7 @@ gp_status gp_step_literal_n(gp_plan_t* p, void* psi, int64_t nsteps) {
   const double nl = p->d.beta * (back ? -p->d.dt : p->d.dt);
   for (int64_t s = 0; s < n; ++s) {
     for (int half = 0; half < 2; ++half) {
-      if ((st = fwd3_unnorm(p, psi)) != GP_OK) return st;
-      launch_mult3(p->prec, psi, p->d.n[0], p->d.n[1], p->d.n[2], p->ax[0].nat[th], p->ax[1].nat[th],
-                   p->ax[2].nat[th], p->stream);
-      if ((st = check_launch(p)) != GP_OK) return st;
+      if ((st = fwd3_mult3(p, psi, th)) != GP_OK) return st;
       if ((st = inv3_unnorm(p, psi)) != GP_OK) return st;
       if (half == 0) {
         launch_nonlinear(p->prec, psi, p->ntot, nl, p->stream);
