@@ -366,11 +366,46 @@ def passes_mode(gp, torch, spec, reps, tune=False, variants=None, rotating=False
     return 0
 
 
-def oracle_sample(psi0_np, w):
-    """The CPU oracle on a bounded sample: one literal Strang step of the same 256^3 field;
-    beside it, seconds per step at 32^3 ... 128^3 (the same construction) for context."""
+def _ensemble_member_step(args):
+    """One literal Strang step of one ensemble member by the oracle (a pool task)."""
+    import numpy as np
     import gp_inputs as I
     from oracle import gp as O
+    from threadpoolctl import threadpool_limits
+    r, K, dt = args
+    psi = np.exp(1j * I.srp_fourier_theta(r["n"], K, r["seed"]))
+    with threadpool_limits(1):              # one core per worker (the pool forks a threaded BLAS)
+        t = time.perf_counter()
+        O.strang_step(psi, r["alpha"], r["beta"], dt)
+        return float(r["n"]) ** 3, time.perf_counter() - t
+
+
+def oracle_sample(psi0_np, w, ensemble=True):
+    """The CPU oracle on a bounded sample: one literal Strang step of the same 256^3 field;
+    beside it, seconds per step at 32^3 ... 128^3 (the same construction), their
+    N^3 log N extrapolation to the 1024^3 workload, and the ensemble's members run
+    one per host core (a process pool started before the GPU is touched)."""
+    import gp_inputs as I
+    from oracle import gp as O
+    out = {}
+    if ensemble:
+        # 16 members in the ensemble's size mix (10 at 64^3, 6 at 96^3), one process per
+        # core, one step each; BLAS single-threaded in every worker
+        import concurrent.futures as cf
+        import multiprocessing as mp
+        ew = I.WORKLOADS["ens48"]
+        runs = ew["runs"][:10] + ew["runs"][32:38]
+        procs = min(len(runs), os.cpu_count() or 1)
+        t = time.perf_counter()
+        with cf.ProcessPoolExecutor(procs, mp_context=mp.get_context("fork")) as ex:
+            res = list(ex.map(_ensemble_member_step, [(r, ew["K"], ew["dt"]) for r in runs]))
+        wall = time.perf_counter() - t
+        pts = sum(p for p, _ in res)
+        out["ensemble_aggregate"] = {
+            "value": pts / wall, "unit": "grid-point.steps/s (summed over runs)", "cores": procs,
+            "sample": f"one literal Strang step of each of {len(runs)} ensemble members (10 at 64^3, 6 at 96^3), "
+                      f"one process per core, {wall:.2f} s wall (pool start included)",
+            "seconds_per_member_step": {f"{r['n']}^3 seed {r['seed']}": s for r, (_, s) in zip(runs, res)}}
     t = time.perf_counter()
     O.strang_step(psi0_np, w["alpha"], w["beta"], w["dt"])
     dt = time.perf_counter() - t
@@ -382,10 +417,16 @@ def oracle_sample(psi0_np, w):
         O.strang_step(psi, w["alpha"], w["beta"], w["dt"])
         sizes[str(n)] = time.perf_counter() - t1
     sizes["256"] = dt
-    return {"value": npts / dt, "unit": "grid-point.steps/s", "cores": 1, "kind": "oracle",
+    # the 1024^3 workload from the 256^3 time under N^3 log N (both FFT-path sizes)
+    t1024 = dt * 64.0 * (10.0 / 8.0)
+    base = {"value": npts / dt, "unit": "grid-point.steps/s", "cores": 1, "kind": "oracle",
             "sample": f"one literal Strang step (4 3-D FFTs, numpy FP64, single thread) of the 256^3 "
                       f"tg256 field, {dt:.1f} s on {cpu_model()}; diagnostics (1 per 100 steps) not included",
-            "seconds": dt, "seconds_per_step_by_n": sizes, "host_cpus": os.cpu_count()}
+            "seconds": dt, "seconds_per_step_by_n": sizes, "host_cpus": os.cpu_count(),
+            "extrapolated_1024": {"seconds_per_step": t1024, "value": 1024.0 ** 3 / t1024,
+                                  "rule": "256^3 time x (1024/256)^3 x log2(1024)/log2(256), one core"}}
+    base.update(out)
+    return base
 
 
 def main(argv=None):
@@ -415,9 +456,17 @@ def main(argv=None):
         return 2
 
     import numpy as np
-    import torch
 
     import gp_inputs as I
+
+    cpu = None
+    if not (a.passes or a.argle or a.no_cpu_baseline):
+        # the CPU oracle first: its process pool forks before the GPU runtime is loaded
+        wb = I.WORKLOADS[WORKLOAD]
+        cpu = oracle_sample(I.tg_psi(wb["n"], wb["ic"][1]["xi"], wb["ic"][1]["exponent"]), wb)
+
+    import torch
+
     import paper_2003_03590_amd as gp
 
     if a.passes:
@@ -494,8 +543,8 @@ def main(argv=None):
                                workload="rvr1024: 1024^3 complex64, timed inside large_1024_c64")
     else:
         res["roofline"] = res["roofline_tg256_c128"]
-    if not a.no_cpu_baseline:
-        res["cpu_baseline"] = oracle_sample(psi0, w)
+    if cpu is not None:
+        res["cpu_baseline"] = cpu
     print(json.dumps(res))
     return 0
 
