@@ -136,8 +136,10 @@ def literal_form(torch, plan, psi0_np, step_ms_merged, steps=10):
 
 def ensemble_form(gp, torch, I):
     """The 48-run ensemble (32 at 64^3, 16 at 96^3, complex64, dt = 1e-3, 300 steps)
-    advanced by one HIP-graph launch after autotuning; grid-point.steps/s summed
-    over runs and the per-run drift of mass and energy."""
+    advanced by one gp_step_n_batch call after autotuning (recorded step graphs:
+    the opening half step, bodies of 128, 128, 32, 8, 2 and 1 applications, the
+    closing half step; the two size groups on parallel branches);
+    grid-point.steps/s summed over runs and the per-run drift of mass and energy."""
     import numpy as np
     w = I.WORKLOADS["ens48"]
     runs = [dict(r, dt=w["dt"]) for r in w["runs"]]
@@ -169,8 +171,13 @@ def ensemble_form(gp, torch, I):
             "plane_pass_runs": int(sum(plane)),
             "max_dN": float(np.max(np.abs(e1[:, 0] - e0[:, 0]) / e0[:, 0])),
             "max_dE": float(np.max(np.abs(e1[:, 1] - e0[:, 1]) / e0[:, 1])),
-            "launch": "one HIP graph of grouped pass launches (one launch per size group and pass, "
-                      "the runs of a group on the second grid dimension)"}
+            "launch": "8 launches of 8 recorded step graphs (opening half step, bodies of 128, 128, 32, 8, 2, 1 "
+                      "applications, closing half step), each with one grouped pass launch per size group "
+                      "and pass (the runs of a group on the second grid dimension) and the two size groups "
+                      "on parallel branches",
+            "copy_reference": "the 48 states total 0.18 GB and fit the 256 MB last-level cache, so this "
+                              "rate is not an HBM figure; the HBM copy reference is "
+                              "large_1024_c64.roofline.copy_gbs"}
 
 
 def large_form(gp, torch, I, steps=5):

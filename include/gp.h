@@ -98,8 +98,8 @@ GP_API gp_status gp_plan(const gp_desc* d, void* hip_stream, gp_plan_t** out);
 
 /* Create a plan for an ensemble of independent runs (grid sizes may differ;
  * all runs share one precision).  Runs are advanced together by
- * gp_step_n_batch, which groups runs of equal size into single launches and
- * records the whole sequence of launches as one HIP graph. */
+ * gp_step_n_batch, which groups runs of equal size into single launches inside
+ * recorded HIP graphs. */
 GP_API gp_status gp_plan_batch(const gp_desc* runs, int32_t nruns, void* hip_stream, gp_plan_t** out);
 
 GP_API gp_status gp_plan_destroy(gp_plan_t* p);
@@ -275,9 +275,15 @@ typedef struct {
 GP_API gp_status gp_argle_run(gp_plan_t* p, void* phi, const void* v, double dtau, int64_t max_steps,
                               int64_t check_every, double eps, void* work, gp_argle_report* report);
 
-/* Ensemble: advance run i's state psis[i] (host array of dev pointers) by nsteps.
- * The first call for a given set of pointers and nsteps records a HIP graph;
- * later identical calls replay it. */
+/* Ensemble: advance run i's state psis[i] (host array of dev pointers) by nsteps
+ * (negative: backward).  The merged sequence L(h) [N L(dt)]^(n-1) N L(h) runs as
+ * recorded HIP graphs: the opening half step, bodies of 2^j applications
+ * (j = 0..7; the 128-application body repeated, the rest by the binary digits of
+ * n - 1) and the closing half step.  Each graph holds one grouped launch per size
+ * group and pass, the size groups on parallel branches; a graph is recorded on
+ * first use for the given states and replayed after, so a call launches at most
+ * 2 + 7 + (n-1)/128 graphs of at most 3 x 128 launches per group, whatever n.
+ * New state pointers, gp_autotune or gp_select_variant drop the recorded graphs. */
 GP_API gp_status gp_step_n_batch(gp_plan_t* p, void* const* psis, int64_t nsteps);
 
 /* Ensemble: mass and energy of every run (host out, 2 * nruns doubles:

@@ -279,9 +279,10 @@ class Plan:
 
 
 class BatchPlan:
-    """Ensemble of independent runs (sizes may differ) advanced by one HIP graph
-    launch: one grouped pass launch per size group and pass (runs of one size share
-    it, run = second grid dimension), recorded once per step count."""
+    """Ensemble of independent runs (sizes may differ) advanced by recorded HIP
+    graphs: one grouped pass launch per size group and pass (runs of one size share
+    it, run = second grid dimension), the size groups on parallel graph branches;
+    a call of n steps replays the opening, 2^j-step body and closing graphs."""
 
     def __init__(self, runs, prec="c64", device=None, stream=None):
         torch = _torch()

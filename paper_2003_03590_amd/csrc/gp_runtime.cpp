@@ -201,10 +201,14 @@ struct gp_plan_s {
   std::vector<gp_plan_s*> runs;
   struct Group { int n; std::vector<int> members; RunPtrs* d_ptrs = nullptr; size_t nptrs = 0; };
   std::vector<Group> groups;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t graph_exec = nullptr;
-  std::vector<void*> graph_key;
-  int64_t graph_steps = 0;
+  // recorded step graphs, [sign: 0 forward, 1 backward][slot]: slot 0 the opening
+  // half step L(h), 1 the closing [N, L(h)], 2 + j the body [N, L(dt)] x 2^j
+  static constexpr int GPOW = 8, GSLOTS = 2 + GPOW;
+  hipGraphExec_t gexec[2][GSLOTS] = {};
+  std::vector<void*> graph_key;      // the states the recorded graphs and tables refer to
+  std::vector<hipStream_t> side;     // capture branches of size groups 1, 2, ...
+  hipEvent_t fork_ev = nullptr;
+  std::vector<hipEvent_t> join_ev;
 };
 
 namespace gpk {
@@ -445,14 +449,25 @@ gp_status plan_init(gp_plan_s* p, const gp_desc* d, hipStream_t stream) {
 void plan_free(gp_plan_s* p) {
   if (!p) return;
   for (auto* r : p->runs) plan_free(r);
-  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
-  if (p->graph) (void)hipGraphDestroy(p->graph);
+  for (auto& row : p->gexec)
+    for (auto& x : row) if (x) (void)hipGraphExecDestroy(x);
+  for (auto st : p->side) if (st) (void)hipStreamDestroy(st);
+  for (auto ev : p->join_ev) if (ev) (void)hipEventDestroy(ev);
+  if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
   for (void* a : p->allocs) (void)hipFree(a);
   for (auto& g : p->groups) if (g.d_ptrs) (void)hipFree(g.d_ptrs);
   if (p->h_result) (void)hipHostFree(p->h_result);
   if (p->rot.work) (void)hipFree(p->rot.work);
   if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
   delete p;
+}
+
+// the recorded step graphs of a batch plan are stale (kernels, tables or states changed)
+void drop_graphs(gp_plan_s* p) {
+  for (auto& row : p->gexec)
+    for (auto& x : row)
+      if (x) { (void)hipGraphExecDestroy(x); x = nullptr; }
+  p->graph_key.clear();
 }
 
 gp_status validate_desc(const gp_desc* d) {
@@ -847,9 +862,7 @@ gp_status gp_select_variant(gp_plan_t* p, int32_t axis, int32_t variant) {
     for (auto* r : p->runs)
       if (r->plane.e || variant == 0)
         if ((st = gp_select_variant(r, 3, variant)) != GP_OK) return st;
-    if (p->graph_exec) { (void)hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
-    if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
-    p->graph_steps = 0;
+    drop_graphs(p);
     return GP_OK;
   }
   if (axis == 3) {   // xy plane: 0 = separate x and y passes, 1 = one plane pass
@@ -1512,90 +1525,133 @@ gp_status gp_plan_batch(const gp_desc* runs, int32_t nruns, void* hip_stream, gp
   p->nshell = p->runs[0]->nshell;
   p->ntot = p->runs[0]->ntot;
   p->own_stream = own_stream;
+  // one capture branch per further size group, so the groups' launches of a step
+  // graph are independent nodes that may run side by side
+  for (size_t g = 1; g < p->groups.size(); ++g) {
+    hipStream_t st2 = nullptr;
+    hipEvent_t ev = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&st2, hipStreamNonBlocking);
+    if (e == hipSuccess) p->side.push_back(st2);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) p->join_ev.push_back(ev);
+    if (e != hipSuccess) { plan_free(p); return fail(GP_ERR_HIP, "capture branch: %s", hipGetErrorString(e)); }
+  }
+  if (p->groups.size() > 1) {
+    hipError_t e = hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming);
+    if (e != hipSuccess) { plan_free(p); return fail(GP_ERR_HIP, "capture fork event: %s", hipGetErrorString(e)); }
+  }
   *out = p;
   g_err.clear();
   return GP_OK;
 }
 
-static gp_status batch_record(gp_plan_s* p, void* const* psis, int64_t nsteps) {
-  gp_status st;
-  const bool back = nsteps < 0;
-  const int64_t n = back ? -nsteps : nsteps;
-  const int th = back ? TAU_MH : TAU_H, tf = back ? TAU_MDT : TAU_DT;
-  // per group: RunPtrs[axis][tau in {h, full}][member]
+// pointer tables of the grouped launches, both signs:
+// RunPtrs[sign][axis][tau: 0 half step, 1 full step][member] per group
+static gp_status batch_tables(gp_plan_s* p, void* const* psis) {
+  // a launch of a recorded graph may still read the tables: let it finish
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  drop_graphs(p);
   for (auto& g : p->groups) {
     const size_t m = g.members.size();
-    std::vector<RunPtrs> h(3 * 2 * m);
-    for (int a = 0; a < 3; ++a)
-      for (int t = 0; t < 2; ++t)
-        for (size_t i = 0; i < m; ++i) {
-          gp_plan_s* r = p->runs[g.members[i]];
-          RunPtrs& e = h[(a * 2 + t) * m + i];
-          e.in = psis[g.members[i]];
-          e.out = psis[g.members[i]];
-          e.mult = r->ax[a].mult[t == 0 ? th : tf];
-          e.nl_coef = r->d.beta * (back ? -r->d.dt : r->d.dt);
-          if (a == 0 && r->plane.on) {   // the x slot carries the plane pass's x and y tables
-            e.mult = r->plane.mx[t == 0 ? th : tf];
-            e.mult2 = r->plane.my[t == 0 ? th : tf];
+    std::vector<RunPtrs> h(2 * 3 * 2 * m);
+    for (int sg = 0; sg < 2; ++sg)
+      for (int a = 0; a < 3; ++a)
+        for (int t = 0; t < 2; ++t)
+          for (size_t i = 0; i < m; ++i) {
+            gp_plan_s* r = p->runs[g.members[i]];
+            const int tau = sg ? (t == 0 ? TAU_MH : TAU_MDT) : (t == 0 ? TAU_H : TAU_DT);
+            RunPtrs& e = h[((sg * 3 + a) * 2 + t) * m + i];
+            e.in = psis[g.members[i]];
+            e.out = psis[g.members[i]];
+            e.mult = r->ax[a].mult[tau];
+            e.nl_coef = r->d.beta * (sg ? -r->d.dt : r->d.dt);
+            if (a == 0 && r->plane.on) {   // the x slot carries the plane pass's x and y tables
+              e.mult = r->plane.mx[tau];
+              e.mult2 = r->plane.my[tau];
+            }
           }
-        }
-    // a launch of the previous graph may still read the table: let it finish
-    HIPCHK(p, hipStreamSynchronize(p->stream));
     if (g.nptrs < h.size()) {
       if (g.d_ptrs) (void)hipFree(g.d_ptrs);
       g.d_ptrs = nullptr;
+      g.nptrs = 0;
       HIPCHK(p, hipMalloc((void**)&g.d_ptrs, h.size() * sizeof(RunPtrs)));
       g.nptrs = h.size();
     }
     HIPCHK(p, hipMemcpy(g.d_ptrs, h.data(), h.size() * sizeof(RunPtrs), hipMemcpyHostToDevice));
   }
-  if (p->graph_exec) { (void)hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
-  if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+  p->graph_key.assign(psis, psis + p->runs.size());
+  return GP_OK;
+}
+
+// record one step graph: slot 0 = L(h); 1 = N, L(h); 2 + j = (N, L(dt)) x 2^j, with the
+// nonlinear rotation fused into each application's first pass; size group g > 0 is
+// captured on its own branch (fork from and join into the plan's stream)
+static gp_status batch_record(gp_plan_s* p, int sg, int slot) {
+  const int64_t reps = slot < 2 ? 1 : (int64_t)1 << (slot - 2);
+  const int t = slot < 2 ? 0 : 1;
+  const bool nl = slot != 0;
   HIPCHK(p, hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
-  auto grouped = [&](const gp_plan_s::Group& g, int a, int t, int var) -> void {
-    gp_plan_s* r = p->runs[g.members[0]];
-    const Axis& A = r->ax[a];
-    const size_t m = g.members.size();
-    PassArgs args{};
-    args.batch = g.d_ptrs + (a * 2 + t) * m;
-    args.tw = A.tw; args.ksq = A.ksq; args.scale = 1.0;
-    args.npencils = A.npencils; args.inner = A.inner; args.outer = A.outer; args.es = A.es;
-    A.e->fn[A.kind][var](args, A.blocks, (unsigned)m, p->stream);
-  };
-  auto grouped_plane = [&](const gp_plan_s::Group& g, int t, bool nl) -> void {
-    gp_plan_s* r = p->runs[g.members[0]];
-    const size_t m = g.members.size();
-    PlaneArgs args{};
-    args.batch = g.d_ptrs + (0 * 2 + t) * m;
-    args.tw = r->plane.tw;
-    r->plane.e->fn[nl ? 1 : 0](args, (unsigned)r->d.n[2], (unsigned)m, p->stream);
-  };
-  for (const auto& g : p->groups) {
+  hipError_t ce = hipSuccess;
+  if (p->groups.size() > 1) ce = hipEventRecord(p->fork_ev, p->stream);
+  for (size_t gi = 0; gi < p->groups.size() && ce == hipSuccess; ++gi) {
+    const auto& g = p->groups[gi];
+    hipStream_t st = gi == 0 ? p->stream : p->side[gi - 1];
+    if (gi > 0) ce = hipStreamWaitEvent(st, p->fork_ev, 0);
+    if (ce != hipSuccess) break;
     gp_plan_s* r0 = p->runs[g.members[0]];
     const int c = first_real_axis(r0);
-    if (c < 0) continue;     // 1x1x1 runs are not batched
-    if (r0->plane.on) {      // every member of the group made the same choice
-      grouped_plane(g, 0, false);
-      if (r0->ax[2].n > 1) grouped(g, 2, 0, V_PROP);
-      for (int64_t s = 0; s < n; ++s) {
-        grouped_plane(g, s + 1 < n ? 1 : 0, true);
-        if (r0->ax[2].n > 1) grouped(g, 2, s + 1 < n ? 1 : 0, V_PROP);
+    const size_t m = g.members.size();
+    auto ptrs = [&](int a) { return g.d_ptrs + ((sg * 3 + a) * 2 + t) * m; };
+    for (int64_t k = 0; k < reps; ++k) {
+      if (r0->plane.on) {      // every member of the group made the same choice
+        PlaneArgs args{};
+        args.batch = ptrs(0);
+        args.tw = r0->plane.tw;
+        r0->plane.e->fn[nl ? 1 : 0](args, (unsigned)r0->d.n[2], (unsigned)m, st);
+        if (r0->ax[2].n > 1) {
+          const Axis& A = r0->ax[2];
+          PassArgs pa{};
+          pa.batch = ptrs(2); pa.tw = A.tw; pa.ksq = A.ksq; pa.scale = 1.0;
+          pa.npencils = A.npencils; pa.inner = A.inner; pa.outer = A.outer; pa.es = A.es;
+          A.e->fn[A.kind][V_PROP](pa, A.blocks, (unsigned)m, st);
+        }
+        continue;
       }
-      continue;
+      for (int a = 0; a < 3; ++a) {
+        if (r0->ax[a].n == 1) continue;
+        const Axis& A = r0->ax[a];
+        PassArgs pa{};
+        pa.batch = ptrs(a); pa.tw = A.tw; pa.ksq = A.ksq; pa.scale = 1.0;
+        pa.npencils = A.npencils; pa.inner = A.inner; pa.outer = A.outer; pa.es = A.es;
+        A.e->fn[A.kind][(nl && a == c) ? V_PROP_NL : V_PROP](pa, A.blocks, (unsigned)m, st);
+      }
     }
-    for (int a = 0; a < 3; ++a) if (r0->ax[a].n > 1) grouped(g, a, 0, V_PROP);
-    for (int64_t s = 0; s < n; ++s)
-      for (int a = 0; a < 3; ++a)
-        if (r0->ax[a].n > 1) grouped(g, a, s + 1 < n ? 1 : 0, a == c ? V_PROP_NL : V_PROP);
+    if (gi > 0) {
+      ce = hipEventRecord(p->join_ev[gi - 1], st);
+      if (ce == hipSuccess) ce = hipStreamWaitEvent(p->stream, p->join_ev[gi - 1], 0);
+    }
   }
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamEndCapture(p->stream, &graph);
-  if (e != hipSuccess) { p->broken = true; return fail(GP_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e)); }
-  p->graph = graph;
-  HIPCHK(p, hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0));
-  p->graph_key.assign(psis, psis + p->runs.size());
-  p->graph_steps = nsteps;
+  if (ce != hipSuccess || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    p->broken = true;
+    return fail(GP_ERR_HIP, "step graph capture: %s", hipGetErrorString(ce != hipSuccess ? ce : e));
+  }
+  e = hipGraphInstantiate(&p->gexec[sg][slot], graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    p->gexec[sg][slot] = nullptr;
+    p->broken = true;
+    return fail(GP_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  return GP_OK;
+}
+
+static gp_status batch_launch(gp_plan_s* p, int sg, int slot) {
+  gp_status st;
+  if (!p->gexec[sg][slot] && (st = batch_record(p, sg, slot)) != GP_OK) return st;
+  HIPCHK(p, hipGraphLaunch(p->gexec[sg][slot], p->stream));
   return GP_OK;
 }
 
@@ -1609,11 +1665,24 @@ gp_status gp_step_n_batch(gp_plan_t* p, void* const* psis, int64_t nsteps) {
   if (nsteps == 0) return GP_OK;
   for (const auto* r : p->runs)
     if (first_real_axis(r) < 0) return fail(GP_ERR_UNSUPPORTED, "1x1x1 runs cannot be batched");
-  const bool same = p->graph_exec && p->graph_steps == nsteps &&
+  const bool same = p->graph_key.size() == p->runs.size() &&
                     std::equal(p->graph_key.begin(), p->graph_key.end(), psis);
-  if (!same && (st = batch_record(p, psis, nsteps)) != GP_OK) return st;
-  HIPCHK(p, hipGraphLaunch(p->graph_exec, p->stream));
-  return GP_OK;
+  if (!same && (st = batch_tables(p, psis)) != GP_OK) return st;
+  // L(h) [N L(dt)]^(n-1) N L(h): the body's n - 1 applications as recorded graphs of
+  // 2^j applications each (the largest repeated, the rest by the binary digits), so a
+  // call of any length launches a bounded set of graphs of bounded size
+  const int sg = nsteps < 0 ? 1 : 0;
+  int64_t rem = (nsteps < 0 ? -nsteps : nsteps) - 1;
+  if ((st = batch_launch(p, sg, 0)) != GP_OK) return st;
+  constexpr int top = gp_plan_s::GPOW - 1;
+  while (rem >= ((int64_t)1 << top)) {
+    if ((st = batch_launch(p, sg, 2 + top)) != GP_OK) return st;
+    rem -= (int64_t)1 << top;
+  }
+  for (int j = top - 1; j >= 0; --j)
+    if (rem & ((int64_t)1 << j))
+      if ((st = batch_launch(p, sg, 2 + j)) != GP_OK) return st;
+  return batch_launch(p, sg, 1);
 }
 
 gp_status gp_energies_batch(gp_plan_t* p, void* const* psis, void* work, double* out) {
@@ -1942,10 +2011,8 @@ gp_status gp_autotune(gp_plan_t* p, void* scratch, int32_t reps, const char* cac
           if ((st = gp_select_variant(p->runs[g.members[i]], a, chosen[a])) != GP_OK) return st;
         }
     }
-    // kernels and tables changed: the recorded graph is stale
-    if (p->graph_exec) { (void)hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
-    if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
-    p->graph_steps = 0;
+    // kernels and tables changed: the recorded graphs are stale
+    drop_graphs(p);
   }
   write_cache(cache_path, cache);
   return GP_OK;

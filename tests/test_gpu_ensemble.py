@@ -104,6 +104,32 @@ def test_ensemble_matches_single_plans_96_128(prec):
     bp.close()
 
 
+def test_ensemble_step_lengths_compose_from_recorded_graphs():
+    """A call of n steps launches the recorded graphs of the opening half step, the
+    body's n - 1 applications by binary digits (up to 128 per graph) and the
+    closing half step: lengths 1, 2, 3, 130 and 257 forward and -5 backward, on
+    three size groups (three capture branches), against single-grid plans."""
+    import paper_2003_03590_amd as gp
+    runs = [dict(n=32, alpha=0.2, beta=10.0, dt=1e-3), dict(n=48, alpha=6.4 / 48, beta=15.0, dt=1e-3),
+            dict(n=32, alpha=0.2, beta=10.0, dt=1e-3), dict(n=64, alpha=0.1, beta=20.0, dt=1e-3)]
+    bp = gp.BatchPlan(runs, "c128")
+    init = [I.random_field(r["n"], seed=600 + i, amp_noise=0.1) for i, r in enumerate(runs)]
+    states = [_dev(a, "c128") for a in init]
+    refs = [_dev(a, "c128") for a in init]
+    plans = [gp.Plan(r["n"], r["alpha"], r["beta"], r["dt"], "c128") for r in runs]
+    for n in (1, 2, 3, 130, 257, -5):
+        bp.step_n(states, n)
+        for p, ref in zip(plans, refs):
+            p.step_n(ref, n)
+        torch.cuda.synchronize()
+        for i in range(len(runs)):
+            rel = float(torch.linalg.vector_norm(states[i] - refs[i]) / torch.linalg.vector_norm(refs[i]))
+            assert rel < 1e-12, (n, i, rel)
+    for p in plans:
+        p.close()
+    bp.close()
+
+
 def test_ensemble_orders_with_the_callers_stream():
     """States written by torch on the current stream just before the call, and read
     right after a long ensemble launch, with no explicit synchronisation: the
