@@ -13,7 +13,8 @@ time-evolution section):
 * forward transform ``c_k = N^-d * sum_x f(x) exp(-i k.x)`` (normalised);
 * inverse transform ``f(x) = sum_k c_k exp(+i k.x)``.
 
-Two independent 1-D engines are provided:
+Two independent 1-D engines are provided (and, for measuring the FP64 floor
+between correct implementations only, ``library_engine``):
 
 * ``dft_axis``   -- the definition itself: a dense N x N matrix
   ``W[j, k] = exp(-2*pi*i*((j*k) mod N)/N)`` applied along one axis, O(N^2);
@@ -110,6 +111,22 @@ def fft_axis(a: np.ndarray, axis: int, sign: int = -1) -> np.ndarray:
     a = np.asarray(a, dtype=np.complex128)
     moved = np.ascontiguousarray(np.moveaxis(a, axis, -1))
     return np.moveaxis(_fft_last(moved, sign), -1, axis)
+
+
+def library_engine(workers: int = 1):
+    """A third, independent 1-D engine: scipy's FFT (pocketfft) as a library
+    primitive, unnormalised in both directions like the two above.  Used only to
+    measure how far two correct FP64 implementations of the same split step drift
+    apart over a long run (their twiddles and operation orders round
+    differently), which is the floor against which a GPU run is judged."""
+    import scipy.fft as sf
+
+    def engine(a, axis, sign):
+        a = np.asarray(a, dtype=np.complex128)
+        if sign < 0:
+            return sf.fft(a, axis=axis, norm="backward", workers=workers)
+        return sf.ifft(a, axis=axis, norm="forward", workers=workers)
+    return engine
 
 
 def transform_axis(a: np.ndarray, axis: int, sign: int, engine: str | None = None) -> np.ndarray:

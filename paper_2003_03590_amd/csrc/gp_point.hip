@@ -295,10 +295,10 @@ __global__ __launch_bounds__(64) void k_spectral(const void* F0, const void* F1,
   // point of the pair with the smaller index.  The pair counts twice, except that a
   // point that is its own mirror counts once, and a point with a Nyquist component
   // (whose mirror index keeps the wavenumber -N/2, so it is not -k) has its mirror
-  // evaluated with the mirror's own wavenumbers.  Each lane takes R consecutive
-  // points along x and adds a shell's terms in registers until the shell changes,
-  // then once into the LDS bins.
-  constexpr int R = 4;
+  // evaluated with the mirror's own wavenumbers.  Consecutive lanes take
+  // consecutive points (coalesced loads, the mirror loads in descending order);
+  // a lane adds its points' terms in registers while they stay in one shell and
+  // only then into the LDS bins.
   extern __shared__ double bins[];            // [4][nshell]
   for (int i = threadIdx.x; i < 4 * nshell; i += 64) bins[i] = 0.0;
   __syncthreads();
@@ -309,12 +309,10 @@ __global__ __launch_bounds__(64) void k_spectral(const void* F0, const void* F1,
   const long i1 = (i0 + chunk < nh) ? i0 + chunk : nh;
   const void* F[4] = {F0, F1, F2, F3};
   auto nyq = [](int i, int nn) { return (nn % 2 == 0) && 2 * i == nn; };
-  for (long base = i0 + (long)threadIdx.x * R; base < i1; base += 64L * R) {
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    int cur = -1;
-    for (int r = 0; r < R; ++r) {
-      const long i = base + r;
-      if (i >= i1) break;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  int cur = -1;
+  {
+    for (long i = i0 + threadIdx.x; i < i1; i += 64) {
       const int ix = (int)(i % nx), iy = (int)((i / nx) % ny), iz = (int)(i / ((long)nx * ny));
       const int mx = (nx - ix) % nx, my = (ny - iy) % ny, mz = (nz - iz) % nz;
       const long m = (long)mz * nx * ny + (long)my * nx + mx;
@@ -348,10 +346,10 @@ __global__ __launch_bounds__(64) void k_spectral(const void* F0, const void* F1,
 #pragma unroll
       for (int q = 0; q < 4; ++q) acc[q] += d[q];
     }
-    if (cur >= 0) {
+  }
+  if (cur >= 0) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) atomicAdd(&bins[q * nshell + cur], acc[q]);
-    }
+    for (int q = 0; q < 4; ++q) atomicAdd(&bins[q * nshell + cur], acc[q]);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < 4 * nshell; i += 64) bins_partial[(long)i * gridDim.x + blockIdx.x] = bins[i];

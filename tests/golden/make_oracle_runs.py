@@ -20,9 +20,14 @@ Fixtures (``tests/golden/oracle_<name>.npz``):
   diagnostics, the density structure function, psi on six pencils;
 * ``ens48``  -- the 48 smoothed-random-phase ensemble members (complex64-rounded
   start, as the complex64 runs see it), 300 steps of dt = 1e-3: mass and energy
-  every 50 steps and psi on six pencils at the end.
+  every 50 steps and psi on six pencils at the end;
+* ``tg256_libfft``, ``rvr256_libfft`` -- the first two runs again with every
+  transform done by the library FFT (``oracle.fft.library_engine``), psi on the
+  same pencils at every checkpoint: two correct FP64 implementations side by
+  side, whose distance is the complex128 parity floor of the long runs.
 
-Usage: python tests/golden/make_oracle_runs.py {tg256,rvr256,ens48,--selftest}
+Usage: python tests/golden/make_oracle_runs.py
+       {tg256,rvr256,ens48,tg256-libfft,rvr256-libfft,--selftest}
        [--workers P] [--save-dir DIR]
 ``--save-dir`` keeps the full state at every checkpoint (for resuming: an
 interrupted run restarts from the last saved state).
@@ -207,6 +212,38 @@ def run_field(name, workers, save_dir):
     print(f"{name}: done in {time.time() - t0:.0f} s", flush=True)
 
 
+def run_field_library(name, workers):
+    """The same FP64 run with the oracle's transforms done by the library FFT
+    (``oracle.fft.library_engine``): psi on the same pencils at every checkpoint.
+    Against ``oracle_<name>.npz`` it measures how far two correct FP64
+    implementations drift apart over the run (the complex128 parity floor)."""
+    w = I.WORKLOADS[name]
+    n, alpha, beta, dt, steps, every = w["n"], w["alpha"], w["beta"], w["dt"], w["steps"], w["diag_every"]
+    kind, ic = w["ic"]
+    t0 = time.time()
+    pos = pencil_positions(n)
+    checks = list(range(0, steps + 1, every))
+    rec = {"steps": np.array(checks), "pencils": np.full((len(checks), len(pos), n), np.nan + 0j),
+           "pencil_pos": pos, "done": np.array(0)}
+    out = os.path.join(HERE, f"oracle_{name}_libfft.npz")
+    if kind == "tg":
+        psi = I.tg_psi(n, ic["xi"], ic["exponent"])
+    else:
+        gen = PoolEngine((n, n, n), workers)
+        psi = gen.rvr(n, ic["xi"], ic["n_pairs"], ic["seed"])
+        gen.close()
+    eng = OF.library_engine(workers)
+    for c, step in enumerate(checks):
+        if step:
+            psi = O.evolve(psi, alpha, beta, dt, every, engine=eng)
+        for p, (axis, i, j) in enumerate(pos):
+            rec["pencils"][c, p] = take_pencil(psi, axis, i, j)
+        _save(out, **rec)
+        print(f"{name} (library FFT): step {step} ({time.time() - t0:.0f} s)", flush=True)
+    rec["done"] = np.array(1)
+    _save(out, **rec)
+
+
 def _ens_member(args):
     r, dt, steps, every, K = args
     n = r["n"]
@@ -264,7 +301,8 @@ def selftest(workers):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["tg256", "rvr256", "ens48", "--selftest", "selftest"])
+    ap.add_argument("what", choices=["tg256", "rvr256", "ens48", "tg256-libfft", "rvr256-libfft",
+                                     "--selftest", "selftest"])
     ap.add_argument("--workers", type=int, default=max(1, (os.cpu_count() or 2) - 1))
     ap.add_argument("--save-dir", default="")
     a = ap.parse_args()
@@ -274,6 +312,8 @@ def main():
         selftest(a.workers)
     elif a.what == "ens48":
         run_ensemble(a.workers)
+    elif a.what.endswith("-libfft"):
+        run_field_library(a.what[:-len("-libfft")], a.workers)
     else:
         run_field(a.what, a.workers, a.save_dir)
 

