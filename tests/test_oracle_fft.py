@@ -60,3 +60,19 @@ def test_engines_agree_3d():
     rng = np.random.default_rng(3)
     psi = rng.standard_normal((24, 16, 12)) + 1j * rng.standard_normal((24, 16, 12))
     assert np.abs(F.fft3(psi, "dft") - F.fft3(psi, "fft")).max() < 1e-15 * 24 * 16 * 12 + 1e-14
+
+
+@pytest.mark.parametrize("n", [2, 3, 12, 48, 64, 96])
+def test_library_engine_equals_the_definition(n):
+    """The library-FFT engine (used only to measure the FP64 floor between two
+    implementations) is the unnormalised transform of the definition in both
+    directions, along every axis."""
+    rng = np.random.default_rng(n)
+    a = rng.standard_normal((n, 3, 5)) + 1j * rng.standard_normal((n, 3, 5))
+    eng = F.library_engine(2)
+    for axis in range(3):
+        b = np.moveaxis(a, 0, axis)
+        for sign in (-1, 1):
+            want = F.dft_axis(b, axis, sign)
+            got = F.transform_axis(b, axis, sign, eng)
+            assert np.abs(got - want).max() < 1e-13 * max(1.0, np.abs(want).max())
