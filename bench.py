@@ -233,7 +233,7 @@ def large_form(gp, torch, I, steps=5):
     # place, or layout-rotating passes through one more state)
     chosen = plan.schedule(5)
     forms = {}
-    for v, name in ((0, "fixed"), (1, "rotating")):
+    for v, name in ((0, "fixed"), (1, "rotating"), (2, "rotating+contiguous")):
         plan.select_variant(5, v)
         plan.step_n(psi, 2)
         torch.cuda.synchronize()
@@ -246,18 +246,22 @@ def large_form(gp, torch, I, steps=5):
                        "axis_pass_gbs": per_launch * launches / (fms / 1e3) / 1e9,
                        "frac": per_launch * launches / (fms / 1e3) / 1e9 / HBM_PEAK_GBS}
     rot = chosen.startswith("layout: rotating")
-    plan.select_variant(5, 1 if rot else 0)
+    mixed = chosen.startswith("layout: rotating+contiguous")
+    plan.select_variant(5, 2 if mixed else 1 if rot else 0)
     out = {"workload": "rvr1024: 1024^3 complex64, 40 random vortex-ring pairs (seed 1), dt = 2.5e-4",
            "steps": steps, "ms_per_step": ms / steps,
            "value": float(n) ** 3 * steps / (ms / 1e3), "unit": "grid-point.steps/s",
            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": gbs / HBM_PEAK_GBS, "per_launch_bytes": per_launch,
-                        "kernel": ("rot_pass (layout-rotating propagator pass; the nonlinear rotation fused "
+                        "kernel": ("rot_pass twice and axis_pass (x kind, in place) once per step, mean of "
+                                   "the three (the nonlinear rotation fused into the first rot_pass)") if mixed else
+                                  ("rot_pass (layout-rotating propagator pass; the nonlinear rotation fused "
                                    "into the first pass of each step)") if rot else
                                   ("axis_pass (propagator; the nonlinear rotation fused into the carrier "
                                    "axis's pass)"),
                         "per_launch": "one axis pass: reads and writes the whole state once (2 N^3 S bytes)",
-                        "traffic": (pass_traffic("rot_pass_rvr1024_traffic.json") if rot else
+                        "traffic": (pass_traffic("rot_pass_rvr1024_traffic.json") if rot and not mixed else
+                                    None if mixed else
                                     pass_traffic("axis_pass_rvr1024_traffic.json",
                                                  [plan.schedule(ax) for ax in range(3)])),
                         "traffic_source": "profiles/%s_pass_rvr1024_traffic.json (null once the kernel "

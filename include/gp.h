@@ -296,7 +296,8 @@ GP_API const char* gp_last_error(void);
 /* Name of the compiled FFT schedule used for an axis, e.g. "N=256 T=16 W=8 R=16x16".
  * axis 3 names the xy choice: "xy: separate passes" or "xy: plane N=.. T=..";
  * axis 4 the pass that carries the nonlinear rotation ("nl: x pass", ...); axis 5
- * the form of the linear steps ("layout: fixed" or "layout: rotating ...").  For a
+ * the form of the linear steps ("layout: fixed", "layout: rotating ..." or
+ * "layout: rotating+contiguous ...").  For a
  * batch plan the index is 6 * run + axis (the names of that run's schedules). */
 GP_API const char* gp_schedule_name(const gp_plan_t* p, int32_t axis);
 
@@ -313,13 +314,17 @@ GP_API const char* gp_schedule_name(const gp_plan_t* p, int32_t axis);
  * linear step (variant 0, 1, 2 = x, y, z; the linear sub-steps commute, so any
  * order is the same split step); default: the first axis of length > 1.  axis 5
  * (single cubic plans) selects the form of the linear steps of gp_step_n: variant
- * 0 (default) the fixed layout, every pass in place; variant v >= 1 the v-th
- * compiled rotating schedule: layout-rotating passes along x, z, y, each reading whole contiguous pencils and writing the state
+ * 0 (default) the fixed layout, every pass in place; variant v = 1..R (R compiled
+ * rotating schedules for the length) the v-th rotating schedule: layout-rotating
+ * passes along x, z, y, each reading whole contiguous pencils and writing the state
  * in a turned layout ([z][y][x] -> [y][x][z] -> [x][z][y] -> [z][y][x]), out of
  * place between psi and one more state that the plan allocates on selection (N^3 S
- * bytes, released again by variant 0); psi holds the [z][y][x] state whenever
- * gp_step_n returns.  GP_ERR_UNSUPPORTED for other shapes or lengths without a
- * rotating schedule.  Batch plans: GP_ERR_STATE for every axis but 3. */
+ * bytes, released again by variant 0); variant R + v the same schedule in the
+ * mixed form: per linear step two rotating passes and one in-place pass along the
+ * axis they leave innermost, so the layout advances one place per step and returns
+ * every three.  psi holds the [z][y][x] state whenever gp_step_n returns.
+ * GP_ERR_UNSUPPORTED for other shapes or lengths without a rotating schedule.
+ * Batch plans: GP_ERR_STATE for every axis but 3. */
 GP_API int32_t gp_variant_count(int32_t n, int32_t prec);
 GP_API gp_status gp_select_variant(gp_plan_t* p, int32_t axis, int32_t variant);
 

@@ -190,6 +190,7 @@ struct gp_plan_s {
   struct Rot {
     const RotEntry* e = nullptr;
     bool on = false;
+    bool mixed = false;            // two rotating passes and one in-place x-kind pass per linear step
     void* work = nullptr;          // N^3 S bytes, allocated when first selected
     void* tw = nullptr;
     void* mult[NTAU] = {};
@@ -557,23 +558,37 @@ gp_status linear_all(gp_plan_s* p, void* psi, int tau, bool with_nl, double nl) 
 // workspace to `out` ([z][y][x]): in -> [y][x][z] -> [x][z][y] -> [z][y][x].  The
 // passes alternate between the two states, so in = out only after an even number
 // of such steps; `in` and `out` are psi and the workspace in turn.
-gp_status rot_linear(gp_plan_s* p, void* a, void* b, int tau, bool with_nl, double nl) {
+// one layout-rotating pass: the innermost axis of `in` transformed, written to `out`
+// turned ([A][B][C] -> [B][C][A])
+gp_status rot_pass_one(gp_plan_s* p, const void* in, void* out, int tau, bool with_nl, double nl) {
   const RotEntry& e = *p->rot.e;
   const unsigned grid = (unsigned)((long)e.n * e.n / e.sched.W);
   RotArgs g{};
+  g.in = in; g.out = out;
   g.mult = p->rot.mult[tau];
   g.tw = p->rot.tw;
   g.nl_coef = nl;
-  gp_status st;
-  g.in = a; g.out = b;                     // x pass (nonlinear prologue)
   e.fn[with_nl ? 1 : 0](g, grid, p->stream);
-  if ((st = check_launch(p)) != GP_OK) return st;
-  g.in = b; g.out = a;                     // z pass
-  e.fn[0](g, grid, p->stream);
-  if ((st = check_launch(p)) != GP_OK) return st;
-  g.in = a; g.out = b;                     // y pass
-  e.fn[0](g, grid, p->stream);
   return check_launch(p);
+}
+
+// L(tau) as three rotating passes x, z, y: from a to b, back in [z][y][x]
+gp_status rot_linear(gp_plan_s* p, void* a, void* b, int tau, bool with_nl, double nl) {
+  gp_status st;
+  if ((st = rot_pass_one(p, a, b, tau, with_nl, nl)) != GP_OK) return st;   // x (nonlinear prologue)
+  if ((st = rot_pass_one(p, b, a, tau, false, nl)) != GP_OK) return st;     // z
+  return rot_pass_one(p, a, b, tau, false, nl);                             // y
+}
+
+// L(tau) as two rotating passes and one in-place pass along the axis they leave
+// innermost (the x-kind kernel: a cube's axes share lengths and tables): from a
+// through b back to a, the layout advanced by one place in the cycle
+// [z][y][x] -> [x][z][y] -> [y][x][z] -> [z][y][x]
+gp_status mixed_linear(gp_plan_s* p, void* a, void* b, int tau, bool with_nl, double nl) {
+  gp_status st;
+  if ((st = rot_pass_one(p, a, b, tau, with_nl, nl)) != GP_OK) return st;
+  if ((st = rot_pass_one(p, b, a, tau, false, nl)) != GP_OK) return st;
+  return pass(p, 0, V_PROP, a, a, p->ax[0].mult[tau]);
 }
 
 gp_status step_n(gp_plan_s* p, void* psi, int64_t nsteps) {
@@ -583,6 +598,26 @@ gp_status step_n(gp_plan_s* p, void* psi, int64_t nsteps) {
   const int th = back ? TAU_MH : TAU_H, tf = back ? TAU_MDT : TAU_DT;
   const double nl = p->d.beta * (back ? -p->d.dt : p->d.dt);
   gp_status st;
+  if (p->rot.on && p->rot.mixed) {
+    // n + 1 linear steps; three mixed ones bring the layout back, each keeps the state
+    // in psi; a remainder of one runs in place with the fixed-layout passes, of two as
+    // two fully rotating steps (psi -> workspace -> psi); all before the cycles, while
+    // the layout is [z][y][x]
+    auto tau_of = [&](int64_t k) { return (k == 0 || k == n) ? th : tf; };
+    const int64_t r = (n + 1) % 3;
+    int64_t k = 0;
+    if (r == 1) {
+      if ((st = linear_all(p, psi, th, false, 0.0)) != GP_OK) return st;
+      k = 1;
+    } else if (r == 2) {
+      if ((st = rot_linear(p, psi, p->rot.work, tau_of(0), false, nl)) != GP_OK) return st;
+      if ((st = rot_linear(p, p->rot.work, psi, tau_of(1), true, nl)) != GP_OK) return st;
+      k = 2;
+    }
+    for (; k <= n; ++k)
+      if ((st = mixed_linear(p, psi, p->rot.work, tau_of(k), k > 0, nl)) != GP_OK) return st;
+    return GP_OK;
+  }
   if (p->rot.on) {
     // n + 1 linear steps; each rotating one moves the state to the other buffer, so
     // with an odd count the opening half step runs in place with the fixed-layout
@@ -895,14 +930,17 @@ gp_status gp_select_variant(gp_plan_t* p, int32_t axis, int32_t variant) {
       p->sched_name[5] = "layout: fixed";
       return GP_OK;
     }
-    if (variant < 1) return fail(GP_ERR_ARG, "layout variant %d (0 = fixed, 1.. = rotating schedules)", variant);
+    if (variant < 1)
+      return fail(GP_ERR_ARG, "layout variant %d (0 = fixed, 1.. = rotating, then mixed, schedules)", variant);
     const int n = p->d.n[0];
     const bool cube = p->d.n[1] == n && p->d.n[2] == n;
     if (!cube || !find_rot(n, p->prec))
       return fail(GP_ERR_UNSUPPORTED, "no layout-rotating schedule for %dx%dx%d (cubes of a compiled length only)",
                   p->d.n[0], p->d.n[1], p->d.n[2]);
-    const RotEntry* e = find_rot(n, p->prec, variant - 1);
-    if (!e) return fail(GP_ERR_ARG, "no rotating schedule %d for n = %d", variant - 1, n);
+    const int nrot = [&] { int k = 0; while (find_rot(n, p->prec, k)) ++k; return k; }();
+    const bool mixed = variant > nrot;
+    const RotEntry* e = find_rot(n, p->prec, mixed ? variant - nrot - 1 : variant - 1);
+    if (!e) return fail(GP_ERR_ARG, "layout variant %d: %d rotating schedules for n = %d", variant, nrot, n);
     HIPCHK(p, p->stream ? hipStreamSynchronize(p->stream) : hipDeviceSynchronize());
     if (p->rot.e && (p->rot.e->sched.NS != e->sched.NS || p->rot.e->sched.radix[0] != e->sched.radix[0] ||
                      p->rot.e->sched.radix[1] != e->sched.radix[1] || p->rot.e->sched.radix[2] != e->sched.radix[2])) {
@@ -912,9 +950,10 @@ gp_status gp_select_variant(gp_plan_t* p, int32_t axis, int32_t variant) {
     p->rot.e = e;
     if ((st = build_rot(p)) != GP_OK) return st;
     p->rot.on = true;
+    p->rot.mixed = mixed;
     char nm[128];
-    snprintf(nm, sizeof nm, "layout: rotating N=%d T=%d W=%d R=%dx%dx%d", e->n, e->sched.T, e->sched.W,
-             e->sched.radix[0], e->sched.radix[1], e->sched.radix[2]);
+    snprintf(nm, sizeof nm, "layout: %s N=%d T=%d W=%d R=%dx%dx%d", mixed ? "rotating+contiguous" : "rotating", e->n,
+             e->sched.T, e->sched.W, e->sched.radix[0], e->sched.radix[1], e->sched.radix[2]);
     p->sched_name[5] = nm;
     return GP_OK;
   }
@@ -1889,17 +1928,17 @@ static gp_status tune_rot(gp_plan_s* p, void* scratch, int reps, int* choice) {
   const int nrot = [&] { int k = 0; while (find_rot(p->d.n[0], p->prec, k)) ++k; return k; }();
   // the candidates are timed in alternation, twice each, keeping each one's best
   // time: the forms differ by ~10 % and clocks drift between measurements
-  std::vector<double> t(1 + nrot, 1e300);
+  std::vector<double> t(1 + 2 * nrot, 1e300);
   gp_status inner = GP_OK;
   for (int round = 0; round < 2; ++round)
-    for (int v = 0; v <= nrot; ++v) {
+    for (int v = 0; v <= 2 * nrot; ++v) {
       double us = 0;
       if (v == 0) {
         if ((st = time_calls(p, reps, &us, [&] {
                if (inner == GP_OK) inner = linear_all(p, scratch, TAU_DT, true, nl);
              })) != GP_OK)
           return st;
-      } else {
+      } else if (v <= nrot) {
         if ((st = gp_select_variant(p, 5, v)) != GP_OK) return st;
         if ((st = time_calls(p, reps, &us, [&] {       // two steps: back in `scratch`
                if (inner == GP_OK) inner = rot_linear(p, scratch, p->rot.work, TAU_DT, true, nl);
@@ -1907,13 +1946,21 @@ static gp_status tune_rot(gp_plan_s* p, void* scratch, int reps, int* choice) {
              })) != GP_OK)
           return st;
         us *= 0.5;
+      } else {
+        if ((st = gp_select_variant(p, 5, v)) != GP_OK) return st;
+        if ((st = time_calls(p, reps, &us, [&] {       // three steps: the layout's cycle
+               for (int k = 0; k < 3 && inner == GP_OK; ++k)
+                 inner = mixed_linear(p, scratch, p->rot.work, TAU_DT, true, nl);
+             })) != GP_OK)
+          return st;
+        us /= 3.0;
       }
       if (inner != GP_OK) return inner;
       tune_note(p, "layout", 5, v, us);
       t[v] = std::min(t[v], us);
     }
   double best = t[0];
-  for (int v = 1; v <= nrot; ++v)
+  for (int v = 1; v <= 2 * nrot; ++v)
     if (t[v] < TUNE_TIE * best) { best = t[v]; *choice = v; }
   return GP_OK;
 }
@@ -1979,7 +2026,8 @@ static gp_status tune_plan(gp_plan_s* p, void* scratch, int reps, std::map<std::
     const std::string key = tune_key(arch, p, 5);
     int c = 0;
     auto it = cache.find(key);
-    if (it != cache.end() && (it->second == 0 || find_rot(n0, p->prec, it->second - 1))) {
+    const int nrot = [&] { int k = 0; while (find_rot(n0, p->prec, k)) ++k; return k; }();
+    if (it != cache.end() && it->second >= 0 && it->second <= 2 * nrot) {
       c = it->second;
     } else {
       if ((st = tune_rot(p, scratch, reps, &c)) != GP_OK) return st;

@@ -1,6 +1,7 @@
 """Layout-rotating linear steps (gp_select_variant axis 5): every linear step as
 x, z, y passes that each read whole contiguous pencils and write the state in a
-turned layout, out of place between psi and one plan-owned state.  Against the
+turned layout, out of place between psi and one plan-owned state, or (mixed) as
+two such passes and one in-place pass along the axis they leave innermost.  Against the
 oracle on small cubes of both precisions (odd and even step counts, so both
 buffer parities, and backward steps), against the fixed-layout form at 1024^3,
 and the rejected shapes."""
@@ -19,18 +20,23 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+@pytest.mark.parametrize("mixed", [False, True], ids=["rotating", "mixed"])
 @pytest.mark.parametrize("prec", ["c128", "c64"])
 @pytest.mark.parametrize("n", [16, 32, 48, 64])
-def test_rotating_steps_match_oracle(n, prec):
+def test_rotating_steps_match_oracle(n, prec, mixed):
+    """Both rotating forms: every linear step as three rotating passes, or (mixed)
+    as two rotating passes and one in-place pass, the layout advancing one place per
+    step; step counts whose n + 1 leaves every remainder mod 2 and mod 3."""
     import paper_2003_03590_amd as gp
     alpha, beta, dt = 0.3, 4.0, 0.01
     plan = gp.Plan(n, alpha, beta, dt, prec)
-    plan.select_variant(5, 1)
-    assert plan.schedule(5).startswith("layout: rotating")
+    nrot = 1                                    # one rotating schedule per length
+    plan.select_variant(5, 1 + nrot if mixed else 1)
+    assert plan.schedule(5).startswith("layout: rotating+contiguous" if mixed else "layout: rotating N")
     psi0 = I.random_field(n, seed=600 + n)
     base = psi0.astype(np.complex64).astype(np.complex128) if prec == "c64" else psi0
     tol = 1e-12 if prec == "c128" else 2e-6
-    for nsteps in (1, 2, 3, -2):
+    for nsteps in (1, 2, 3, 4, 5, -2):
         psi = torch.from_numpy(base).to(DEV).to(plan.dtype).contiguous()
         plan.step_n(psi, nsteps)
         ref = O.evolve(base, alpha, beta, dt, nsteps)
@@ -71,15 +77,18 @@ def test_rotating_1024_matches_fixed_layout():
     fixed = gp.Plan(n, w["alpha"], w["beta"], w["dt"], "c64")
     rot = gp.Plan(n, w["alpha"], w["beta"], w["dt"], "c64")
     m0 = float(torch.sum(torch.abs(start.to(torch.complex128)) ** 2))
-    rot.select_variant(5, 1)
-    for nsteps in (2, 3):
-        a, b = start.clone(), start.clone()
-        fixed.step_n(a, nsteps)
-        rot.step_n(b, nsteps)
-        rel = float(torch.linalg.vector_norm((a - b).to(torch.complex128)) / torch.linalg.vector_norm(a.to(torch.complex128)))
-        m1 = float(torch.sum(torch.abs(b.to(torch.complex128)) ** 2))
-        print(f"1024^3 rotating vs fixed, {nsteps} steps: rel-L2 {rel:.2e}, mass change {abs(m1 - m0) / m0:.2e}")
-        assert rel < 2e-6 and abs(m1 - m0) / m0 < 1e-6
-        del a, b
+    for variant in (1, 2):                      # rotating, mixed
+        rot.select_variant(5, variant)
+        for nsteps in (2, 3):
+            a, b = start.clone(), start.clone()
+            fixed.step_n(a, nsteps)
+            rot.step_n(b, nsteps)
+            rel = float(torch.linalg.vector_norm((a - b).to(torch.complex128)) /
+                        torch.linalg.vector_norm(a.to(torch.complex128)))
+            m1 = float(torch.sum(torch.abs(b.to(torch.complex128)) ** 2))
+            print(f"1024^3 {rot.schedule(5)} vs fixed, {nsteps} steps: rel-L2 {rel:.2e}, "
+                  f"mass change {abs(m1 - m0) / m0:.2e}")
+            assert rel < 2e-6 and abs(m1 - m0) / m0 < 1e-6
+            del a, b
     fixed.close()
     rot.close()
