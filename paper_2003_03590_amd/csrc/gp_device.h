@@ -105,14 +105,56 @@ constexpr double cos2pi(long m, long R) {
   // rotate by q quadrants: (c, s) -> angle + q*pi/2
   return q == 0 ? c : q == 1 ? -s : q == 2 ? -c : s;
 }
+
+// Unit complex constants as FP64 pairs whose norm is as close to 1 as the format
+// allows.  The transform applies a constant w in the forward pass and conj(w) in
+// the inverse, so every pass multiplies the modes on w's path by |w|^2; a rounded
+// pair has |w|^2 - 1 of up to ~2e-16 (of one sign for the series values of a given
+// radix), which repeats every pass and adds up over a run.  Among the pairs within
+// two units in the last place of (c, s) the one with the smallest |c^2 + s^2 - 1|
+// is taken: the angle moves by a few 1e-16 (a phase, which the inverse undoes), the
+// norm error drops to ~1e-18.
+constexpr void two_prod(double a, double b, double& p, double& e) {   // a b = p + e exactly
+  p = a * b;
+  const double sa = 134217729.0 * a, ah = sa - (sa - a), al = a - ah;
+  const double sb = 134217729.0 * b, bh = sb - (sb - b), bl = b - bh;
+  e = ((ah * bh - p) + ah * bl + al * bh) + al * bl;
+}
+constexpr double norm_err(double c, double s) {                        // c^2 + s^2 - 1
+  double pc = 0, ec = 0, ps = 0, es = 0;
+  two_prod(c, c, pc, ec);
+  two_prod(s, s, ps, es);
+  const double t = pc >= ps ? (pc - 1.0) + ps : (ps - 1.0) + pc;
+  return t + (ec + es);
+}
+constexpr double ulp_step(double x, int k) {                           // k units in the last place
+  return __builtin_bit_cast(double, __builtin_bit_cast(unsigned long long, x) + (long long)k);
+}
+struct Pair { double c, s; };
+constexpr Pair unit_pair(double c, double s) {
+  Pair best{c, s};
+  double be = norm_err(c, s);
+  be = be < 0 ? -be : be;
+  for (int i = -2; i <= 2; ++i)
+    for (int j = -2; j <= 2; ++j) {
+      if ((c == 0.0 && i != 0) || (s == 0.0 && j != 0)) continue;      // exact zeros stay
+      const double cc = ulp_step(c, i), ss = ulp_step(s, j);
+      double e = norm_err(cc, ss);
+      e = e < 0 ? -e : e;
+      if (e < be) { be = e; best = Pair{cc, ss}; }
+    }
+  return best;
+}
 }  // namespace ct
 
 // exp(sgn * 2 pi i m / R) as compile-time constants; sgn = -1 forward, +1 inverse.
+// sin(2 pi m/R) = cos(2 pi m/R - pi/2) = cos(2 pi (4m - R) / (4R)); the pair is the
+// norm-closest one (ct::unit_pair), the same for both signs.
 template <int M, int R, int SGN>
 struct Root {
-  static constexpr double c = ct::cos2pi(M, R);
-  // sin(2 pi m/R) = cos(2 pi m/R - pi/2) = cos(2 pi (4m - R) / (4R))
-  static constexpr double s = SGN * ct::cos2pi(4L * M - R, 4L * R);
+  static constexpr ct::Pair u = ct::unit_pair(ct::cos2pi(M, R), ct::cos2pi(4L * M - R, 4L * R));
+  static constexpr double c = u.c;
+  static constexpr double s = SGN * u.s;
 };
 
 // multiply v by exp(SGN * 2 pi i M / R), with exact special cases

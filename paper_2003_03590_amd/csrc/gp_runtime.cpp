@@ -62,7 +62,8 @@ void cis2pi(long num, long den, double* c, double* s) {
   bool swap = false;
   if (oct % 2 == 0) { a = (M_PI / 4) * double(r) / double(den); }
   else { a = (M_PI / 4) * double(den - r) / double(den); swap = true; }
-  double cc = std::cos(a), ss = std::sin(a);
+  const ct::Pair u = ct::unit_pair(std::cos(a), std::sin(a));    // norm-closest pair
+  double cc = u.c, ss = u.s;
   if (swap) std::swap(cc, ss);        // angle in octant 2q+1 measured from the next axis
   const long q = oct / 2;              // quadrant
   switch (q) {
@@ -333,7 +334,8 @@ gp_status build_tables(gp_plan_s* p, int a) {
     for (int k = 0; k < n; ++k) {
       const double kk = (double)kfreq(k, n);
       const double ph = alpha * kk * kk * taus[t];
-      const double c = std::cos(ph) / n, s = -std::sin(ph) / n;
+      const ct::Pair u = ct::unit_pair(std::cos(ph), std::sin(ph));
+      const double c = u.c / n, s = -u.s / n;
       mp[2 * pos[k]] = c; mp[2 * pos[k] + 1] = s;
       mn[2 * k] = c; mn[2 * k + 1] = s;
     }
@@ -383,8 +385,9 @@ gp_status build_plane_tables(gp_plan_s* p) {
       const double kk = (double)kfreq(k, n);
       const double ph = alpha * kk * kk * taus[t];
       const int i = tab_idx(e, k);
-      m[2 * i] = std::cos(ph) / n;
-      m[2 * i + 1] = -std::sin(ph) / n;
+      const ct::Pair u = ct::unit_pair(std::cos(ph), std::sin(ph));
+      m[2 * i] = u.c / n;
+      m[2 * i + 1] = -u.s / n;
     }
     if ((st = upload_c128(p, &P.mx[t], m)) != GP_OK) return st;
     P.my[t] = P.mx[t];
@@ -665,8 +668,9 @@ gp_status build_rot(gp_plan_s* p) {
       const double kk = (double)kfreq(k, n);
       const double ph = alpha * kk * kk * taus[t];
       const int i = tab_idx(R.e->sched, k);
-      m[2 * i] = std::cos(ph) / n;
-      m[2 * i + 1] = -std::sin(ph) / n;
+      const ct::Pair u = ct::unit_pair(std::cos(ph), std::sin(ph));
+      m[2 * i] = u.c / n;
+      m[2 * i + 1] = -u.s / n;
     }
     if (!R.mult[t] && (st = upload_c128(p, &R.mult[t], m)) != GP_OK) return st;
   }
@@ -1037,8 +1041,9 @@ gp_status gp_substep_linear(gp_plan_t* p, void* psi, int32_t axis, double s) {
     const double kk = (double)kfreq(k, n);
     const double ph = p->d.alpha * kk * kk * s;
     const int ps = tab_idx(*A.e, k);
-    m[2 * ps] = std::cos(ph) / n;
-    m[2 * ps + 1] = -std::sin(ph) / n;
+    const ct::Pair u = ct::unit_pair(std::cos(ph), std::sin(ph));
+    m[2 * ps] = u.c / n;
+    m[2 * ps + 1] = -u.s / n;
   }
   void*& tab = p->substep_tables[{axis, s}];
   if (!tab && (st = upload_c128(p, &tab, m)) != GP_OK) return st;
