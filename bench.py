@@ -260,13 +260,13 @@ def large_form(gp, torch, I, steps=5):
                                   ("axis_pass (propagator; the nonlinear rotation fused into the carrier "
                                    "axis's pass)"),
                         "per_launch": "one axis pass: reads and writes the whole state once (2 N^3 S bytes)",
-                        "traffic": (pass_traffic("rot_pass_rvr1024_traffic.json") if rot and not mixed else
-                                    None if mixed else
+                        "traffic": (pass_traffic("mixed_pass_rvr1024_traffic.json") if mixed else
+                                    pass_traffic("rot_pass_rvr1024_traffic.json") if rot else
                                     pass_traffic("axis_pass_rvr1024_traffic.json",
                                                  [plan.schedule(ax) for ax in range(3)])),
                         "traffic_source": "profiles/%s_pass_rvr1024_traffic.json (null once the kernel "
                                           "sources or schedules differ from the profiled ones)"
-                                          % ("rot" if rot else "axis"),
+                                          % ("mixed" if mixed else "rot" if rot else "axis"),
                         "mean_launch_us": ms * 1e3 / launches,
                         "copy_gbs": copy_gbs, "frac_of_copy": gbs / copy_gbs,
                         "copy": "gp_copy_state: read 8 GiB, write 8 GiB, one 16-byte unit per lane "
