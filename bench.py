@@ -7,11 +7,13 @@ dt = 5e-4, energy decomposition and shell spectra every 100 steps, complex128
 100 Strang steps (gp_step_n) followed by the diagnostics (gp_spectra); the
 default 10 timed bench steps are the workload's 1000 time steps.
 
-Printed: one JSON line with the throughput in grid-point.steps/s, the roofline
-of the axis-pass kernel (HIP events over the timed region), the complex64 form
-at its measured energy drift, the 48-run ensemble, the 1024^3 complex64 workload
-(the axis pass on a state far larger than the last-level cache), and the CPU
-oracle timed on a bounded sample.
+Printed: one JSON line with the throughput in grid-point.steps/s; `roofline`,
+the HBM roofline of the passes of the 1024^3 complex64 workload (an 8 GiB state,
+32 times the last-level cache; HIP events over the timed region, a plain device
+copy of the same bytes beside it); `roofline_tg256_c128`, the headline's axis pass
+on its cache-resident state; the complex64 form at its measured energy drift, the
+literal form, the 48-run ensemble, the 1024^3 layout forms, and the CPU oracle
+timed on a bounded sample.
 """
 from __future__ import annotations
 
