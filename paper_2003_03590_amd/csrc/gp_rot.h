@@ -34,10 +34,10 @@ __global__ __launch_bounds__(S::THREADS) void rot_pass(RotArgs a) {
   using C = cplx<Real>;
   constexpr int T = S::T, W = S::W, E = S::E, N = S::N;
   constexpr int SZ = (int)sizeof(C);
-  static_assert(N % W == 0, "tiles cover whole rows of A");
+  static_assert(N % W == 0 && (W & (W - 1)) == 0, "tiles cover whole rows of A; W a power of two");
   // stage exchanges, and the regrouping of the whole tile (which single-stage
   // schedules need although they have no exchange)
-  constexpr int REGROUP = (N + N / S::RL) * W;
+  constexpr int REGROUP = N * W;
   __shared__ C lds[cmax(cmax(Lds<S, SZ, CONTIG>::ELEMS, Lds<S, SZ, STRIDED>::ELEMS), REGROUP)];
   const int tid = threadIdx.x;
 
@@ -81,14 +81,19 @@ __global__ __launch_bounds__(S::THREADS) void rot_pass(RotArgs a) {
 
   // v[e] holds position t + T e of pencil col; regroup so that lane (t2, col2)
   // holds positions t2 + T e of pencils col2 = tid % W (neighbouring lanes,
-  // neighbouring A)
+  // neighbouring A).  Regroup layout: row p of W columns with the column index
+  // XOR-swizzled by the row, so that neither the writes (consecutive rows of one
+  // column) nor the reads (whole rows) hit a bank twice in one pass (the padded
+  // strided layout had the writes 4- to 8-way conflicted)
+  constexpr bool HALF = (W == 8 && SZ == 8);
+  auto rg = [](int p, int c) { return p * W + (c ^ ((HALF ? (p >> 1) : 3 * p) & (W - 1))); };
   __syncthreads();                        // the last stage exchange has been read
 #pragma unroll
-  for (int e = 0; e < E; ++e) lds[Lds<S, SZ, STRIDED>::addr(t + T * e, col)] = v[e];
+  for (int e = 0; e < E; ++e) lds[rg(t + T * e, col)] = v[e];
   __syncthreads();
   const int col2 = tid % W, t2 = tid / W;
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = lds[Lds<S, SZ, STRIDED>::addr(t2 + T * e, col2)];
+  for (int e = 0; e < E; ++e) v[e] = lds[rg(t2 + T * e, col2)];
   const auto out = gptr_mut<C>(a.out) + b * NN + (long)t2 * N + a0 + col2;
 #pragma unroll
   for (int e = 0; e < E; ++e) out[(long)T * N * e] = v[e];
