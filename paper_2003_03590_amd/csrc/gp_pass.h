@@ -111,22 +111,38 @@ struct Sched {
   static constexpr int RL = rad(NS > 0 ? NS - 1 : 0);     // radix of the last stage
 };
 
+// Lanes of one pencil in the contiguous mapping: TL consecutive lanes on one pencil
+// (a 128-byte segment, or the whole pencil when it is shorter).
+template <class S, int SZ>
+constexpr int lanes_per_pencil() { return (S::T * SZ <= 128) ? S::T : 128 / SZ; }
+
+// Smallest pitch >= n, in points of SZ bytes, that sets the rows of one LDS cycle
+// apart by whole lane groups.  The LDS serves 128 bytes per cycle (16 lanes of a
+// 64-bit access, 8 of a 128-bit one); with TL lanes per row, 128/(SZ TL) rows share a
+// cycle and a pitch of TL modulo 128/SZ points puts each row on its own banks.  With
+// one row per cycle the pitch is kept at 128 B modulo 256 B.
+template <int SZ>
+constexpr int row_pitch(int n, int TL) {
+  int c = n;
+  if (128 % SZ != 0) return c;
+  const int slots = 128 / SZ;
+  if (TL < slots) {
+    while (c % slots != TL % slots) ++c;
+  } else {
+    while (c % (2 * slots) != slots) ++c;
+  }
+  return c;
+}
+
 // LDS layout of the stage exchanges (SZ = bytes per element).
 //   CONTIG  [col][pos + pos/RL + pad]: one pad element every RL positions spreads the
-//           stride-RL accesses of the last stage over the banks; the column pitch is
-//           128 B modulo 256 B so two neighbouring columns use different bank halves.
+//           stride-RL accesses of the last stage over the banks; the column pitch
+//           (row_pitch) gives the pencils that share an LDS cycle different banks.
 //   STRIDED [pos + pos/RL][col]: one pad row every RL rows, for the same reason.
 template <class S, int SZ, int KIND>
 struct Lds {
   static constexpr int PADN = S::N + S::N / S::RL;
-  static constexpr int cpitch() {
-    int c = PADN;
-    if (128 % SZ == 0) {
-      const int mod = 256 / SZ, want = 128 / SZ;
-      while (c % mod != want) ++c;
-    }
-    return c;
-  }
+  static constexpr int cpitch() { return row_pitch<SZ>(PADN, lanes_per_pencil<S, SZ>()); }
   static constexpr int CP = cpitch();
   static constexpr int ELEMS = (S::NS > 1) ? (KIND == CONTIG ? S::W * CP : PADN * S::W) : 1;
   static __device__ __forceinline__ int addr(int pos, int col) {
@@ -358,7 +374,7 @@ __global__ __launch_bounds__(S::THREADS) void axis_pass(PassArgs a) {
   if constexpr (KIND == CONTIG) {
     // TL consecutive points of one pencil form a 128-byte segment; a wavefront
     // covers several pencils per load instruction (spreads requests over channels)
-    constexpr int TL = (T * (int)sizeof(C) <= 128) ? T : 128 / (int)sizeof(C);
+    constexpr int TL = lanes_per_pencil<S, (int)sizeof(C)>();
     t = tid % TL + TL * (tid / (TL * W));
     col = (tid / TL) % W;
   } else {

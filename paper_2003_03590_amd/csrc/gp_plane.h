@@ -31,7 +31,11 @@ template <class Real, class S, int PRO>
 __global__ __launch_bounds__(S::THREADS) void plane_pass(PlaneArgs a) {
   static_assert(S::W == S::N, "a plane workgroup holds all N rows");
   using C = cplx<Real>;
-  constexpr int N = S::N, T = S::T, E = S::E, P = N + 1;   // P: plane row pitch in LDS
+  constexpr int N = S::N, T = S::T, E = S::E;
+  // plane row pitch in LDS: rows that share an LDS cycle in the row-major write get
+  // their own banks (the column reads take consecutive points of one row)
+  constexpr int SZ = (int)sizeof(C), TLX = lanes_per_pencil<S, SZ>();
+  constexpr int P = (TLX < 128 / SZ) ? row_pitch<SZ>(N, TLX) : N + 1;
   constexpr int L = S::NS - 1, B = E / S::rad(L);
   constexpr int EX = Lds<S, (int)sizeof(C), CONTIG>::ELEMS, EY = Lds<S, (int)sizeof(C), STRIDED>::ELEMS;
   // one buffer serves the row exchanges, the plane and the column exchanges in turn
@@ -49,7 +53,7 @@ __global__ __launch_bounds__(S::THREADS) void plane_pass(PlaneArgs a) {
   C v[E];
 
   {  // rows: S(s, L_x) (with the nonlinear prologue)
-    constexpr int TL = (T * (int)sizeof(C) <= 128) ? T : 128 / (int)sizeof(C);
+    constexpr int TL = TLX;
     const int t = tid % TL + TL * (tid / (TL * N));
     const int row = (tid / TL) % N;
     const auto src = gptr<C>(a.in) + base + (long)row * N + t;

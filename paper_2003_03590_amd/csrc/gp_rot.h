@@ -51,7 +51,7 @@ __global__ __launch_bounds__(S::THREADS) void rot_pass(RotArgs a) {
   const long NN = (long)N * N;
 
   // load with the contiguous mapping: TL consecutive lanes on one pencil
-  constexpr int TL = (T * SZ <= 128) ? T : 128 / SZ;
+  constexpr int TL = lanes_per_pencil<S, SZ>();
   const int t = tid % TL + TL * (tid / (TL * W));
   const int col = (tid / TL) % W;
   C v[E];
