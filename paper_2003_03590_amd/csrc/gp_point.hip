@@ -57,6 +57,25 @@ __device__ __forceinline__ int shell_of(long k2) {
 
 __device__ __forceinline__ int kfreq(int i, int n) { return (2 * i < n) ? i : i - n; }  // fftfreq (Nyquist -> -n/2)
 
+// Grid coordinates of linear index i (x fastest).  Indices below 2^32 use 32-bit
+// unsigned division: a 64-bit division is a long software sequence on the GPU, and
+// per point it cost more than the arithmetic of the kernels that need coordinates.
+__device__ __forceinline__ void grid_xyz(long i, int nx, int ny, int& ix, int& iy, int& iz) {
+  if ((unsigned long)i <= 0xFFFFFFFFul) {
+    const unsigned u = (unsigned)i, r = u / (unsigned)nx, q = r / (unsigned)ny;
+    ix = (int)(u - r * (unsigned)nx);
+    iy = (int)(r - q * (unsigned)ny);
+    iz = (int)q;
+  } else {
+    const long r = i / nx, q = r / ny;
+    ix = (int)(i - r * nx);
+    iy = (int)(r - q * ny);
+    iz = (int)q;
+  }
+}
+// index of the mirror point -x on a periodic axis of n points
+__device__ __forceinline__ int mirror_of(int i, int n) { return i ? n - i : 0; }
+
 // ----------------------------------------------------------------- elementwise
 template <class Real>
 __global__ void k_init_phase(const double* __restrict__ theta, void* psi, long n) {
@@ -91,7 +110,8 @@ __global__ void k_mult3(void* f, int nx, int ny, int nz, const void* mx, const v
   const cplx<double>* ty = reinterpret_cast<const cplx<double>*>(my);
   const cplx<double>* tz = reinterpret_cast<const cplx<double>*>(mz);
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    const int ix = (int)(i % nx), iy = (int)((i / nx) % ny), iz = (int)(i / ((long)nx * ny));
+    int ix, iy, iz;
+    grid_xyz(i, nx, ny, ix, iy, iz);
     p[i] = pmul(p[i], cmul(cmul(tx[ix], ty[iy]), tz[iz]));      // product of the factors in FP64
   }
 }
@@ -313,8 +333,9 @@ __global__ __launch_bounds__(64) void k_spectral(const void* F0, const void* F1,
   int cur = -1;
   {
     for (long i = i0 + threadIdx.x; i < i1; i += 64) {
-      const int ix = (int)(i % nx), iy = (int)((i / nx) % ny), iz = (int)(i / ((long)nx * ny));
-      const int mx = (nx - ix) % nx, my = (ny - iy) % ny, mz = (nz - iz) % nz;
+      int ix, iy, iz;
+      grid_xyz(i, nx, ny, ix, iy, iz);
+      const int mx = mirror_of(ix, nx), my = mirror_of(iy, ny), mz = mirror_of(iz, nz);
       const long m = (long)mz * nx * ny + (long)my * nx + mx;
       if (m < i) continue;                    // counted with its mirror
       cplx<Real> z[4], zm[4];
@@ -423,8 +444,9 @@ __global__ __launch_bounds__(256) void k_loss_spectral(void* F0, void* F1, int n
   cplx<Real>* P0 = reinterpret_cast<cplx<Real>*>(F0);
   cplx<Real>* P1 = reinterpret_cast<cplx<Real>*>(F1);
   for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
-    const int ix = (int)(i % nx), iy = (int)((i / nx) % ny), iz = (int)(i / ((long)nx * ny));
-    const long m = (long)((nz - iz) % nz) * nx * ny + (long)((ny - iy) % ny) * nx + (nx - ix) % nx;
+    int ix, iy, iz;
+    grid_xyz(i, nx, ny, ix, iy, iz);
+    const long m = (long)mirror_of(iz, nz) * nx * ny + (long)mirror_of(iy, ny) * nx + mirror_of(ix, nx);
     if (m < i) continue;                       // the pair is handled at its smaller index
     const cplx<Real> z0 = P0[i], z0m = P0[m], z1 = P1[i], z1m = P1[m];
     const int kx = kfreq(ix, nx), ky = kfreq(iy, ny), kz = kfreq(iz, nz);
@@ -790,8 +812,9 @@ __global__ __launch_bounds__(64) void k_hel_spectral(const void* V01, const void
   const long i0 = (long)blockIdx.x * chunk;
   const long i1 = (i0 + chunk < n) ? i0 + chunk : n;
   for (long i = i0 + threadIdx.x; i < i1; i += 64) {
-    const int ix = (int)(i % nx), iy = (int)((i / nx) % ny), iz = (int)(i / ((long)nx * ny));
-    const long m = (long)((nz - iz) % nz) * nx * ny + (long)((ny - iy) % ny) * nx + (nx - ix) % nx;
+    int ix, iy, iz;
+    grid_xyz(i, nx, ny, ix, iy, iz);
+    const long m = (long)mirror_of(iz, nz) * nx * ny + (long)mirror_of(iy, ny) * nx + mirror_of(ix, nx);
     double v[6], r[6], o[6], t0, t1;     // [x re, x im, y re, y im, z re, z im]
     unpack2<Real>(V01, i, m, inv, &v[0], &v[1], &v[2], &v[3]);
     unpack2<Real>(V2, i, m, inv, &v[4], &v[5], &t0, &t1);
@@ -1048,7 +1071,8 @@ __global__ __launch_bounds__(256) void k_init_rvr(const RingPar* __restrict__ pa
   const double two_pi = 6.283185307179586476925286766559;
   const long n = (long)nx * ny * nz;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    const int ix = (int)(i % nx), iy = (int)((i / nx) % ny), iz = (int)(i / ((long)nx * ny));
+    int ix, iy, iz;
+    grid_xyz(i, nx, ny, ix, iy, iz);
     const double c[3] = {two_pi * ix / nx, two_pi * iy / ny, two_pi * iz / nz};
     double pr = 1.0, pim = 0.0;
     for (int q = 0; q < npairs; ++q) {
