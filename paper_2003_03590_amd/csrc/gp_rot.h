@@ -82,9 +82,10 @@ __global__ __launch_bounds__(S::THREADS) void rot_pass(RotArgs a) {
   // v[e] holds position t + T e of pencil col; regroup so that lane (t2, col2)
   // holds positions t2 + T e of pencils col2 = tid % W (neighbouring lanes,
   // neighbouring A).  Regroup layout: row p of W columns with the column index
-  // XOR-swizzled by the row, so that neither the writes (consecutive rows of one
-  // column) nor the reads (whole rows) hit a bank twice in one pass (the padded
-  // strided layout had the writes 4- to 8-way conflicted)
+  // XOR-swizzled by the row.  The LDS serves 16 lanes of a 64-bit access (8 of a
+  // 128-bit one) per cycle; with the swizzle neither the writes (consecutive rows of
+  // one column) nor the reads (whole rows) of those lanes meet in a bank when
+  // T >= 8, where the padded strided layout put 8 to 16 of them in one bank
   constexpr bool HALF = (W == 8 && SZ == 8);
   auto rg = [](int p, int c) { return p * W + (c ^ ((HALF ? (p >> 1) : 3 * p) & (W - 1))); };
   __syncthreads();                        // the last stage exchange has been read
