@@ -3,7 +3,7 @@ x, z, y passes that each read whole contiguous pencils and write the state in a
 turned layout, out of place between psi and one plan-owned state, or (mixed) as
 two such passes and one in-place pass along the axis they leave innermost.  Against the
 oracle on small cubes of both precisions (odd and even step counts, so both
-buffer parities, and backward steps), against the fixed-layout form at 1024^3,
+buffer parities, and backward steps), against the fixed-layout form at 512^3 and 1024^3,
 and the rejected shapes."""
 import numpy as np
 import pytest
@@ -89,6 +89,40 @@ def test_rotating_1024_matches_fixed_layout():
             print(f"1024^3 {rot.schedule(5)} vs fixed, {nsteps} steps: rel-L2 {rel:.2e}, "
                   f"mass change {abs(m1 - m0) / m0:.2e}")
             assert rel < 2e-6 and abs(m1 - m0) / m0 < 1e-6
+            del a, b
+    fixed.close()
+    rot.close()
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_rotating_512_matches_fixed_layout(prec):
+    """512^3 (the rotating schedules 8x8x8 complex128 and 32x16 complex64, with the
+    XOR-swizzled LDS regroup): two and three rotating and mixed steps against the
+    fixed-layout passes, within rounding of the different operation order; mass
+    conserved."""
+    import paper_2003_03590_amd as gp
+    w = I.WORKLOADS["rvr1024"]
+    n = 512
+    dt = torch.complex128 if prec == "c128" else torch.complex64
+    tol = 1e-12 if prec == "c128" else 2e-6
+    g = torch.Generator(device=DEV).manual_seed(12)
+    start = torch.randn((n, n, n), dtype=dt, device=DEV, generator=g)
+    start += 1.0
+    fixed = gp.Plan(n, w["alpha"], w["beta"], w["dt"], prec)
+    rot = gp.Plan(n, w["alpha"], w["beta"], w["dt"], prec)
+    m0 = float(torch.sum(torch.abs(start.to(torch.complex128)) ** 2))
+    for variant in (1, 2):                      # rotating, mixed
+        rot.select_variant(5, variant)
+        for nsteps in (2, 3):
+            a, b = start.clone(), start.clone()
+            fixed.step_n(a, nsteps)
+            rot.step_n(b, nsteps)
+            rel = float(torch.linalg.vector_norm((a - b).to(torch.complex128)) /
+                        torch.linalg.vector_norm(a.to(torch.complex128)))
+            m1 = float(torch.sum(torch.abs(b.to(torch.complex128)) ** 2))
+            print(f"512^3 {prec} {rot.schedule(5)} vs fixed, {nsteps} steps: rel-L2 {rel:.2e}, "
+                  f"mass change {abs(m1 - m0) / m0:.2e}")
+            assert rel < tol and abs(m1 - m0) / m0 < tol
             del a, b
     fixed.close()
     rot.close()
